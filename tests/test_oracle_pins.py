@@ -1,0 +1,457 @@
+"""Pins of the CPU reference against what the paper and mathematics fix.
+
+Each test ties a reference function to something other than itself: values the
+paper prints (tests/golden/paper_values.json), closed forms, invariants, library
+routines it must reduce to, or an independent brute force on tiny inputs.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle.lof_oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
+
+
+def golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32)
+
+
+def run(x, dtype=O.F32, **kw):
+    return O.flag_block(x, dtype, O.Params(**kw))
+
+
+# ------------------------------------------------------------------ thresholds
+def test_factor_worked_values_from_paper():
+    g = golden()
+    prm = O.Params(p=g["default_p"]["value"], sensitivity=g["default_sensitivity"]["value"])
+    f = O.level_factors(prm, 2)
+    # Sec. 2.1: 6 sigma at window 1, 4.5 sigma at window 2.
+    assert f[0] * prm.sensitivity == g["first_iteration_sigma"]["value"]
+    assert f[1] * prm.sensitivity == g["second_iteration_sigma"]["value"]
+
+
+def test_factor_closed_form():
+    # startThreshold * p^log2(I) / I with p = 1.5 is 6 * 0.75^k exactly in binary.
+    f = O.level_factors(O.Params(), 10)
+    for k, v in enumerate(f):
+        assert v == 6.0 * 0.75 ** k
+        assert Fraction(v) == Fraction(6) * Fraction(3, 4) ** k
+    assert f[:7] == [6, 4.5, 3.375, 2.53125, 1.8984375, 1.423828125, 1.06787109375]
+
+
+def test_threshold_is_median_plus_scaled_sigma():
+    T = O.thresholds(3.0, 2.0, O.Params(sensitivity=0.5), 3)
+    assert T == [3.0 + 2.0 * 6.0 * 0.5, 3.0 + 2.0 * 4.5 * 0.5, 3.0 + 2.0 * 3.375 * 0.5]
+
+
+# --------------------------------------------------------------- median, stddev
+@pytest.mark.parametrize("n", [1, 2, 3, 10, 11, 1000, 1001])
+def test_median_matches_numpy(n):
+    rng = np.random.default_rng(n)
+    a = rng.integers(0, 50, size=n)
+    assert O.block_median(a) == float(np.median(a))
+    b = rng.standard_normal(n).astype(np.float64)
+    assert O.block_median(b) == float(np.median(b))
+
+
+@pytest.mark.parametrize("n", [1, 7, 64, 4096])
+def test_stddev_matches_numpy_and_exact(n):
+    rng = np.random.default_rng(100 + n)
+    a = rng.integers(0, 32769, size=n).astype(np.int64)
+    sd = O.block_stddev(a, exact=True)
+    s1, s2 = sum(int(v) for v in a), sum(int(v) * int(v) for v in a)
+    var_exact = Fraction(s2, n) - Fraction(s1, n) ** 2
+    ref = math.sqrt(float(var_exact))
+    assert sd == pytest.approx(ref, rel=1e-14, abs=1e-300)
+    assert sd == pytest.approx(float(np.std(a.astype(np.float64))), rel=1e-12, abs=1e-300)
+    b = rng.exponential(1.0, size=n)
+    assert O.block_stddev(b, exact=False) == pytest.approx(float(np.std(b)), rel=1e-12, abs=1e-300)
+
+
+def test_power_definitions():
+    x = np.array([[[3, 4], [-128, -128], [0, 0]]], dtype=np.int8)
+    assert O.power(x, O.CI8).tolist() == [[25, 32768, 0]]
+    z = np.array([[3 + 4j, 1 - 1j]], dtype=np.complex64)
+    assert O.power(z, O.C64).tolist() == [[25.0, 2.0]]
+    assert O.power(z, O.C64_AMP).tolist() == [[5.0, math.sqrt(2.0)]]
+
+
+# ------------------------------------------------------------- SumThreshold pins
+@pytest.mark.parametrize("dtype", [O.F32, O.CI8])
+def test_constant_input_gives_no_flags(dtype):
+    if dtype == O.F32:
+        x = np.full((8, 300), 7.25, dtype=np.float32)
+    else:
+        x = np.zeros((8, 300, 2), dtype=np.int8)
+        x[..., 0] = 5
+        x[..., 1] = -3
+    r = O.flag_block(x, dtype, O.Params())
+    assert r.stddev == 0.0
+    assert not r.flags.any()
+
+
+@pytest.mark.parametrize("N", list(range(28, 44)) + [64, 100])
+def test_single_impulse_flagged_iff_N_at_least_35(N):
+    # Zero background, one impulse: sigma = A sqrt(N-1)/N, so A > 6 sigma iff N >= 35.
+    for A in (1.0, 37.5):
+        x = np.zeros((1, N), dtype=np.float32)
+        x[0, N // 3] = A
+        r = run(x)
+        expect = np.zeros((1, N), dtype=bool)
+        if N >= 35:
+            expect[0, N // 3] = True
+        assert (r.flags == expect).all(), (N, A)
+
+
+def test_single_impulse_exact_path():
+    for N in (34, 35):
+        x = np.zeros((1, N, 2), dtype=np.int8)
+        x[0, 5, 0] = 100
+        r = O.flag_block(x, O.CI8, O.Params())
+        assert r.flags[0, 5] == (N >= 35)
+        assert r.flags.sum() == (1 if N >= 35 else 0)
+
+
+def _box_closed_form(N, w, A=1.0, prm=O.Params()):
+    """Independent derivation for a 1-D box on a zero background: the first level
+    k* with a window whose mean exceeds T_k flags the union of all such windows
+    of that level (windows are judged on the unflagged data)."""
+    b0 = (N - w) // 2
+    frac = w / N
+    sigma = A * math.sqrt(frac * (1 - frac))
+    med = 0.0
+    for k in range(prm.n_levels):
+        I = 1 << k
+        T = med + sigma * prm.start_threshold * 0.75 ** k
+        flagged = np.zeros(N, dtype=bool)
+        for s in range(N - I + 1):
+            ov = max(0, min(s + I, b0 + w) - max(s, b0))
+            if A * ov > I * T:
+                flagged[s:s + I] = True
+        if flagged.any():
+            return k, flagged
+    return None, np.zeros(N, dtype=bool)
+
+
+# (width, first level k*, extra samples flagged on each side) worked on paper.
+BOX_TABLE = [(1, 0, 0), (8, 0, 0), (29, 0, 0), (30, 1, 0), (53, 1, 0), (54, 2, 0),
+             (100, 3, 1), (200, 4, 3), (300, 4, 2)]
+
+
+@pytest.mark.parametrize("w,kstar,ext", BOX_TABLE)
+def test_box_closed_form(w, kstar, ext):
+    N = 1024
+    x = np.zeros((1, N), dtype=np.float32)
+    b0 = (N - w) // 2
+    x[0, b0:b0 + w] = 1.0
+    r = run(x, sir_eta_num=0)
+    k, cf = _box_closed_form(N, w)
+    assert k == kstar
+    expect = np.zeros(N, dtype=bool)
+    expect[max(0, b0 - ext):b0 + w + ext] = True
+    assert (cf == expect).all()
+    assert (r.flags[0] == expect).all()
+    # same on the exact integer path (re = 1 -> power 1)
+    xi = np.zeros((1, N, 2), dtype=np.int8)
+    xi[0, b0:b0 + w, 0] = 1
+    ri = O.flag_block(xi, O.CI8, O.Params(sir_eta_num=0))
+    assert (ri.flags[0] == expect).all()
+
+
+def test_box_2d_detected_per_row():
+    # A w x h box detected by the time pass: each row behaves as the 1-D box.
+    C, N, w, h = 16, 512, 100, 4
+    x = np.zeros((C, N), dtype=np.float32)
+    x[5:5 + h, 200:200 + w] = 1.0
+    r = run(x, sir_eta_num=0)
+    frac = (w * h) / (C * N)
+    sigma = math.sqrt(frac * (1 - frac))
+    rowflag = np.zeros(N, dtype=bool)
+    for k in range(7):
+        I = 1 << k
+        T = sigma * 6 * 0.75 ** k
+        for s in range(N - I + 1):
+            ov = max(0, min(s + I, 300) - max(s, 200))
+            if ov > I * T:
+                rowflag[s:s + I] = True
+        if rowflag.any():
+            break
+    for c in range(C):
+        if 5 <= c < 5 + h:
+            assert (r.st_mask[c] == rowflag).all()
+        else:
+            assert not r.st_mask[c].any()
+
+
+def test_n_levels_one_is_plain_thresholder():
+    rng = np.random.default_rng(5)
+    x = rng.exponential(1.0, size=(16, 700)).astype(np.float32)
+    x[3, 100] = 40.0
+    r = run(x, n_levels=1, sir_eta_num=0)
+    p = x.astype(np.float64)
+    T0 = O.block_median(p) + 6.0 * O.block_stddev(p, False)
+    assert (r.flags == (p > T0)).all()
+
+
+def test_flags_only_accumulate_over_levels():
+    rng = np.random.default_rng(6)
+    p = rng.exponential(1.0, size=(12, 600))
+    p[:, 300:340] += 2.0
+    med, sd = O.block_median(p), O.block_stddev(p, False)
+    T = O.thresholds(med, sd, O.Params())
+    prev = np.zeros(p.shape, dtype=bool)
+    for n in range(1, 8):
+        m = O.sumthreshold_rows(p, np.zeros(p.shape, dtype=bool), T, n, False)
+        assert (m >= prev).all()
+        prev = m
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_time_and_frequency_reversal_symmetry(seed):
+    rng = np.random.default_rng(seed)
+    x = rng.exponential(1.0, size=(24, 400)).astype(np.float32)
+    x[rng.integers(0, 24), :] += 5.0
+    x[:, rng.integers(0, 380):][:, :10] += 8.0
+    x[4:12, 50:90] += 1.5
+    r = run(x)
+    rt = run(x[:, ::-1].copy())
+    rf = run(x[::-1, :].copy())
+    assert (rt.flags == r.flags[:, ::-1]).all()
+    assert (rf.flags == r.flags[::-1, :]).all()
+
+
+def test_power_of_two_scaling_invariance():
+    rng = np.random.default_rng(9)
+    x = rng.exponential(1.0, size=(32, 512)).astype(np.float32)
+    x[7, :] += 6.0
+    x[:, 100:104] += 9.0
+    r1 = run(x)
+    for s in (0.25, 4.0, 1024.0):
+        r2 = run((x * np.float32(s)).astype(np.float32))
+        assert (r1.flags == r2.flags).all()
+
+
+def test_pure_noise_level0_rate():
+    # Exponential power (unit complex noise): P(p > ln2 + 6) = e^{-6}/2 = 1.239e-3.
+    rng = np.random.default_rng(11)
+    p = rng.exponential(1.0, size=(64, 16384))
+    med, sd = O.block_median(p), O.block_stddev(p, False)
+    T = O.thresholds(med, sd, O.Params(), 1)
+    m = O.sumthreshold_rows(p, np.zeros(p.shape, dtype=bool), T, 1, False)
+    rate = m.mean()
+    expect = 0.5 * math.exp(-6.0)
+    n = p.size
+    assert abs(rate - expect) < 5 * math.sqrt(expect / n) + 2e-4
+
+
+def test_frequency_level_one_is_noop_after_time():
+    rng = np.random.default_rng(12)
+    p = rng.exponential(1.0, size=(20, 300))
+    p[3, 7] = 30
+    T = O.thresholds(O.block_median(p), O.block_stddev(p, False), O.Params())
+    m = O.sumthreshold_rows(p, np.zeros(p.shape, dtype=bool), T, 7, False)
+    m1 = O.sumthreshold_rows(p.T, m.T, T, 1, False).T
+    assert (m1 == m).all()
+
+
+def _st_bruteforce_fraction(p_rows, T, n_levels):
+    """Pure-Python per-window SumThreshold with exact rationals (independent loops)."""
+    out = []
+    for row in p_rows:
+        n = len(row)
+        m = [False] * n
+        for k in range(n_levels):
+            I = 1 << k
+            if I > n:
+                break
+            nm = list(m)
+            for s in range(n - I + 1):
+                vals = [row[j] for j in range(s, s + I) if not m[j]]
+                if vals and Fraction(sum(vals)) > len(vals) * Fraction(T[k]):
+                    for j in range(s, s + I):
+                        nm[j] = True
+            m = nm
+        out.append(m)
+    return np.array(out, dtype=bool)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_tiny_exhaustive_vs_rational_bruteforce(seed):
+    rng = np.random.default_rng(1000 + seed)
+    C, T = int(rng.integers(1, 7)), int(rng.integers(1, 9))
+    x = rng.integers(-6, 7, size=(C, T, 2)).astype(np.int8)
+    if seed % 3 == 0:
+        x[rng.integers(0, C), :, 0] = 60
+    prm = O.Params(start_threshold=float(rng.choice([0.5, 1.0, 2.0, 6.0])), sir_eta_num=0)
+    r = O.flag_block(x, O.CI8, prm)
+    p = O.power(x, O.CI8)
+    th = r.thresholds
+    m = _st_bruteforce_fraction([list(map(int, row)) for row in p], th, prm.n_levels)
+    mt = _st_bruteforce_fraction([list(map(int, col)) for col in p.T], th, prm.n_levels)
+    # frequency pass starts from the time mask: run it column by column
+    cols = []
+    for t in range(T):
+        col = [int(v) for v in p[:, t]]
+        mcol = [bool(v) for v in m[:, t]]
+        n = len(col)
+        for k in range(prm.n_levels):
+            I = 1 << k
+            if I > n:
+                break
+            nm = list(mcol)
+            for s in range(n - I + 1):
+                vals = [col[j] for j in range(s, s + I) if not mcol[j]]
+                if vals and Fraction(sum(vals)) > len(vals) * Fraction(th[k]):
+                    for j in range(s, s + I):
+                        nm[j] = True
+            mcol = nm
+        cols.append(mcol)
+    expect = np.array(cols, dtype=bool).T
+    assert (r.st_mask == expect).all()
+    del mt
+
+
+# ------------------------------------------------------------------------- SIR
+@pytest.mark.parametrize("num,den", [(1, 5), (1, 2), (2, 5), (0, 1), (1, 1)])
+def test_sir_linear_equals_bruteforce(num, den):
+    rng = np.random.default_rng(num * 10 + den)
+    for _ in range(150):
+        n = int(rng.integers(1, 40))
+        m = rng.random(n) < rng.uniform(0.05, 0.7)
+        lin = O.sir_rows(m[None, :], num, den)[0]
+        bf = O.sir_row_bruteforce(m, num, den)
+        assert (lin == bf).all(), (m.astype(int), num, den)
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 5, 7, 8, 12, 20, 40, 41])
+def test_sir_isolated_run_closed_form(L):
+    # eta = 0.2: a run of L grows by floor(eta L / (1 - eta)) = floor(L / 4) per side.
+    n = 200
+    m = np.zeros(n, dtype=bool)
+    m[80:80 + L] = True
+    out = O.sir_rows(m[None, :], 1, 5)[0]
+    e = L // 4
+    expect = np.zeros(n, dtype=bool)
+    expect[80 - e:80 + L + e] = True
+    assert (out == expect).all()
+
+
+def test_sir_properties():
+    rng = np.random.default_rng(3)
+    for _ in range(100):
+        n = int(rng.integers(1, 80))
+        a = rng.random(n) < 0.3
+        b = a | (rng.random(n) < 0.1)
+        sa = O.sir_rows(a[None], 1, 5)[0]
+        sb = O.sir_rows(b[None], 1, 5)[0]
+        assert (sa >= a).all()                       # extensive
+        assert (sb >= sa).all()                      # monotone
+        assert (O.sir_rows(a[None], 0, 5)[0] == a).all()   # eta = 0: identity
+
+
+def test_sir_block_is_time_then_frequency():
+    rng = np.random.default_rng(4)
+    m = rng.random((9, 30)) < 0.25
+    got = O.sir_block(m, O.Params())
+    rows = np.array([O.sir_row_bruteforce(r, 1, 5) for r in m])
+    expect = np.array([O.sir_row_bruteforce(c, 1, 5) for c in rows.T]).T
+    assert (got == expect).all()
+
+
+def test_sir_percentage_from_paper():
+    g = golden()
+    prm = O.Params()
+    assert prm.sir_eta_num / prm.sir_eta_den == g["sir_percentage"]["value"]
+
+
+# --------------------------------------------------------------------- history
+def test_history_worked_sequences():
+    prm = O.Params(history_sensitivity=6.0)
+    ring = [10.0, 10.0, 10.0, 10.0]
+    assert O.history_row(40, 4, ring, prm) == (False, 10.0)      # cur = thr: not flagged
+    assert O.history_row(42, 4, ring, prm) == (True, 10.0)       # cur > thr: push thr
+    lit = O.Params(literal_history_tie=True)
+    assert O.history_row(40, 4, ring, lit) == (True, 10.0)
+    # ring [1,2,3,4]: mean 2.5, population var 1.25
+    prm1 = O.Params(history_sensitivity=1.0)
+    thr = 2.5 + math.sqrt(1.25)
+    assert O.history_row(3.6, 1, [1.0, 2.0, 3.0, 4.0], prm1) == (False, 3.6)
+    f, v = O.history_row(3.7, 1, [1.0, 2.0, 3.0, 4.0], prm1)
+    assert f and v == thr
+    # warm-up: fewer than history_min entries -> never flags, pushes cur
+    assert O.history_row(1e9, 1, [1.0, 1.0, 1.0], prm) == (False, 1e9)
+    # fully flagged channel: no flag, no push
+    assert O.history_row(0, 0, ring, prm) == (False, None)
+
+
+def test_history_ring_and_constant_stream():
+    prm = O.Params(history_len=5, history_min=2)
+    h = O.History(prm)
+    x = np.full((3, 64), 2.0, dtype=np.float32)
+    for i in range(12):
+        r = O.flag_block(x, O.F32, prm, history=h, stream_id=7)
+        assert not r.flags.any()
+        h.commit()
+    assert len(h.ring(7, 0)) == 5 and h.ring(7, 0) == [2.0] * 5
+    lit = O.Params(history_len=5, history_min=2, literal_history_tie=True)
+    h2 = O.History(lit)
+    got = []
+    for i in range(5):
+        r = O.flag_block(x, O.F32, lit, history=h2, stream_id=0)
+        got.append(bool(r.history_rows.all()))
+        h2.commit()
+    assert got == [False, False, True, True, True]
+
+
+def test_history_flags_broadband_step():
+    prm = O.Params(history_len=8, history_min=4)
+    h = O.History(prm)
+    rng = np.random.default_rng(21)
+    flagged = []
+    for i in range(10):
+        x = rng.exponential(1.0, size=(4, 256)).astype(np.float32)
+        if i == 8:
+            x *= 3.0   # a broadband level change longer than the block
+        r = O.flag_block(x, O.F32, prm, history=h, stream_id=0)
+        flagged.append(bool(r.history_rows.all()))
+        h.commit()
+    assert flagged[8] and not any(flagged[:8])
+
+
+def test_history_sizing_from_paper():
+    g = golden()
+    a = g["history_precorrelation"]
+    per_s = O.history_bytes_per_second(a["stations"], a["subbands"], a["channels"], a["bytes"])
+    assert round(per_s / 2 ** 20, 1) == a["mbyte_per_s"]
+    assert round(per_s * a["entries_5min"] / 2 ** 30, 1) == a["gbyte_5min"]
+    b = g["history_postcorrelation"]
+    per_s = O.history_bytes_per_second(b["baselines"], b["subbands"], b["channels"], b["bytes"])
+    assert round(per_s / 2 ** 20) == b["mbyte_per_s"]
+    assert round(per_s * b["entries_5min"] / 2 ** 30) == b["gbyte_5min"]
+
+
+# ---------------------------------------------------------------- end to end
+def test_injected_rfi_is_found_config0_shape():
+    import synth
+    x, dt = synth.config0()
+    r = O.flag_block(x, dt, O.Params())
+    rng = synth.rng_for(0, 0)
+    # regenerate the plan exactly as the generator drew it
+    rng.standard_normal((64, 4096), dtype=np.float32)
+    rng.standard_normal((64, 4096), dtype=np.float32)
+    plan = synth.rfi_plan(rng, 64, 4096)
+    for kind, c0, c1, t0, t1, k, _ in plan:
+        frac = r.flags[c0:c1, t0:t1].mean()
+        if kind in ("tone", "impulse"):
+            assert frac > 0.9, (kind, frac)
+    assert r.flags.mean() < 0.2
