@@ -1,0 +1,171 @@
+/*
+ * lof.h -- C ABI of the MI355X (gfx950) LOFAR Online Flagger hot path.
+ *
+ * Method: van Nieuwpoort, "Towards exascale real-time RFI mitigation",
+ * arXiv 1701.08197.  Per time-frequency block the library computes
+ *   power |x|^2 (or amplitude, or takes power as given)           -- Sec. 4
+ *   block median and population standard deviation                 -- Sec. 2.1, 4.2
+ *   threshold_I = median + stddev * factor_I * sensitivity,
+ *   factor_I = startThreshold * p^log2(I) / I, I = 1, 2, 4, ...    -- Sec. 2.1
+ *   SumThreshold along time, then along frequency                  -- Sec. 2.1
+ *   the scale-invariant rank (SIR) operator, time then frequency   -- Sec. 2.2
+ *   the history flagger against per-channel statistics of earlier
+ *   blocks of the same stream                                      -- Sec. 4.1
+ * and writes one flag byte per sample.  All work runs in HIP kernels on the
+ * device; the host side only validates, lays out descriptors and enqueues.
+ *
+ * Conventions shared by every call:
+ *  - All calls are asynchronous with respect to the host: they validate their
+ *    arguments synchronously (all-or-nothing: an invalid call enqueues nothing
+ *    and changes no state) and then enqueue work on `hip_stream` (a hipStream_t
+ *    passed as void*, NULL = the legacy default stream).
+ *  - Pointers inside lof_block and the `stats` array are DEVICE pointers owned
+ *    by the caller; they must stay valid until the work enqueued on the stream
+ *    has completed.  Host arrays (the lof_block array, stream id lists) are
+ *    read during the call only.
+ *  - A lof_ctx is not thread-safe.  Calls on different HIP streams may overlap
+ *    on the device as long as they do not name the same history stream id while
+ *    both are in flight (the history ring of that id would race).
+ *  - Device faults surface as LOF_ERR_DEVICE on a later call.
+ *  - lof_last_error() returns a static description of the last failure.
+ */
+#ifndef LOF_H
+#define LOF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lof_ctx lof_ctx;
+
+typedef enum {
+  LOF_OK = 0,
+  LOF_ERR_INVALID = -1,   /* bad argument (nothing enqueued, no state change)   */
+  LOF_ERR_NOMEM = -2,     /* device or pinned-host allocation failed (create)   */
+  LOF_ERR_DEVICE = -3,    /* a HIP runtime call failed                           */
+  LOF_ERR_CAPACITY = -4   /* request exceeds the capacities given to lof_create */
+} lof_status;
+
+/* Sample types (Sec. 4: voltages need power first; visibilities are flagged on
+ * amplitude; beam-formed data is Stokes I as given). */
+typedef enum {
+  LOF_CI8 = 0,     /* complex int8, interleaved (re, im) bytes; power re^2+im^2 is an
+                      exact integer, so flags are exact                              */
+  LOF_C64 = 1,     /* complex64 (float re, float im); power in float32                */
+  LOF_F32 = 2,     /* float32 power / Stokes I, flagged as given                      */
+  LOF_C64_AMP = 3  /* complex64 visibilities; amplitude sqrt(re^2+im^2) in float32    */
+} lof_dtype;
+
+/* Option bits for lof_params.options */
+#define LOF_OPT_AUTOCOMMIT 0x1u          /* lof_flag_blocks also commits the history
+                                            values it staged (same enqueue)          */
+#define LOF_OPT_LITERAL_HISTORY_TIE 0x2u /* history flags when cur >= thr (the Sec. 4.1
+                                            listing's else-branch) instead of cur > thr */
+
+#define LOF_MAX_LEVELS 16
+#define LOF_MAX_CHANNELS 1024
+#define LOF_MAX_BLOCK_SAMPLES (1LL << 23)
+
+typedef struct {
+  double start_threshold;      /* startThreshold of factor_I (Sec. 2.1); 6.0 gives the
+                                  6 sigma first iteration                            */
+  double p;                    /* factor base (Sec. 2.1), 1.5                         */
+  double sensitivity;          /* Sec. 2.1, 1.0                                       */
+  int32_t n_levels;            /* SumThreshold iterations along time, I = 1..2^(n-1)
+                                  (Sec. 2.1: 7-10); a level with I > extent is skipped;
+                                  1..LOF_MAX_LEVELS-1                                 */
+  int32_t n_levels_freq;       /* iterations along frequency; -1 = same as n_levels  */
+  int32_t sir_eta_num;         /* SIR eta = num/den (Sec. 2.2: 20 % -> 1/5);          */
+  int32_t sir_eta_den;         /* num = 0 disables SIR; 0 <= num <= den, den <= 1024  */
+  double history_sensitivity;  /* history threshold = mean + this * stddev of the
+                                  committed means (Sec. 4.1)                          */
+  int32_t history_len;         /* H, committed means kept per (stream, channel)      */
+  int32_t history_min;         /* no history flagging until this many are committed  */
+  int32_t max_streams;         /* history stream ids are 0..max_streams-1             */
+  int32_t max_channels;        /* ring capacity per stream; also the block C limit   */
+  int32_t max_blocks_per_call;
+  int32_t _reserved0;
+  int64_t max_samples_per_call;/* sum of C*T over one lof_flag_blocks call            */
+  uint32_t options;            /* LOF_OPT_* bits                                      */
+  int32_t _reserved1;
+} lof_params;
+
+typedef struct {
+  const void* data;            /* device pointer: row c starts at element c*data_row_stride;
+                                  element size 2 (CI8), 8 (C64, C64_AMP) or 4 (F32) bytes */
+  uint8_t* flags;              /* device pointer: output, byte 0/1 per sample; row c
+                                  starts at byte c*flag_row_stride                    */
+  int64_t data_row_stride;     /* elements between channel rows, >= n_times           */
+  int64_t flag_row_stride;     /* bytes between channel rows, >= n_times              */
+  int32_t n_channels;          /* C: 1..max_channels (and <= LOF_MAX_CHANNELS)        */
+  int32_t n_times;             /* T: >= 1; C*T <= LOF_MAX_BLOCK_SAMPLES               */
+  int32_t dtype;               /* lof_dtype                                          */
+  int32_t stream_id;           /* history key (e.g. station, pol, subband) in
+                                  [0, max_streams), or -1 for no history; an id may
+                                  appear at most once per call                       */
+} lof_block;
+
+typedef struct {
+  double median;               /* block median (Sec. 2.1)                            */
+  double stddev;               /* block population stddev                            */
+  double threshold[LOF_MAX_LEVELS]; /* threshold_I for I = 2^k, k < n_levels          */
+  int64_t n_flagged;           /* flagged samples in the final output                */
+  int32_t history_flagged_rows;/* channels flagged by the history flagger            */
+  int32_t _pad;
+} lof_block_stats;
+
+/* Fills *params with the defaults: startThreshold 6, p 1.5, sensitivity 1,
+ * 7 levels both ways, SIR eta 1/5, history sensitivity 6, H 32, warm-up 4,
+ * capacities 1 stream x 64 channels, 1 block, 2^23 samples.  Sec. 2.1, 2.2, 4.1. */
+lof_status lof_default_params(lof_params* params);
+
+/* Creates a flagger on HIP device `hip_device`.  Allocates every device buffer
+ * the later calls need (history rings sized max_streams*max_channels*history_len
+ * float64, descriptor and scratch slots sized by the per-call maxima); later
+ * calls never allocate.  Returns LOF_ERR_INVALID for bad parameters (no device
+ * work done), LOF_ERR_NOMEM / LOF_ERR_DEVICE on allocation or HIP failures.
+ * *out receives the context (NULL on failure). */
+lof_status lof_create(const lof_params* params, int hip_device, lof_ctx** out);
+
+/* Flags `n_blocks` independent blocks (Sec. 4.1: one block per station,
+ * polarisation and subband per time chunk), writing each block's flags.
+ * `blocks` is a HOST array.  `stats` is a DEVICE array of n_blocks entries or
+ * NULL; entry i describes blocks[i].  For blocks with stream_id >= 0 the history
+ * flagger reads only the committed history of that id and stages one value per
+ * channel for lof_history_update (a fully flagged channel stages nothing); a
+ * second flag call for the same id before the commit replaces the staged values.
+ * n_blocks = 0 is a no-op.  Errors: LOF_ERR_INVALID (null ctx/blocks, bad shape,
+ * stride, dtype, stream id out of range or repeated), LOF_ERR_CAPACITY (more
+ * blocks or samples than the create-time maxima, C > max_channels). */
+lof_status lof_flag_blocks(lof_ctx* ctx, const lof_block* blocks, int32_t n_blocks,
+                           void* hip_stream, lof_block_stats* stats);
+
+/* Commits the staged history values (Sec. 4.1 addToHistory) of the listed stream
+ * ids (HOST array of n ids), or of every stream when stream_ids is NULL.  Ids
+ * with nothing staged are a no-op.  Each (stream, channel) ring keeps its last
+ * history_len values.  Errors: LOF_ERR_INVALID for ids out of range or n < 0. */
+lof_status lof_history_update(lof_ctx* ctx, const int32_t* stream_ids, int32_t n,
+                              void* hip_stream);
+
+/* Copies the committed history to HOST arrays (synchronous: waits for the
+ * stream): values[s][c][j] oldest-first for j < counts[s][c] (rest 0),
+ * counts[s][c], staged[s][c] and staged_valid[s][c], for s < max_streams,
+ * c < max_channels, j < history_len.  Any output may be NULL.  Checkpointing
+ * and tests. */
+lof_status lof_history_export(lof_ctx* ctx, double* values, int32_t* counts,
+                              double* staged, uint8_t* staged_valid, void* hip_stream);
+
+/* Frees the context.  The caller must have synchronised every stream used with
+ * it.  NULL is a no-op. */
+lof_status lof_destroy(lof_ctx* ctx);
+
+/* Static, NUL-terminated description of the last error on ctx (or of the last
+ * failed lof_create when ctx is NULL). */
+const char* lof_last_error(const lof_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LOF_H */

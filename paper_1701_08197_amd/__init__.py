@@ -1,0 +1,8 @@
+"""MI355X (gfx950) implementation of the LOFAR Online Flagger hot path
+(van Nieuwpoort, arXiv 1701.08197): power, block median and stddev,
+SumThreshold in time then frequency, SIR operator, history flagger, all in HIP
+kernels behind the C ABI of include/lof.h."""
+from . import _native  # noqa: F401
+from ._native import (LOF_CI8, LOF_C64, LOF_F32, LOF_C64_AMP, LOF_OPT_AUTOCOMMIT,  # noqa: F401
+                      LOF_OPT_LITERAL_HISTORY_TIE, STATS_BYTES)
+from .flagger import Block, Flagger, LofError, decode_stats, default_params  # noqa: F401

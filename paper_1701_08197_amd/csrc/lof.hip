@@ -1,0 +1,415 @@
+// lof.hip -- host side of the C ABI declared in include/lof.h, and the kernel
+// instantiations.  Method: van Nieuwpoort, "Towards exascale real-time RFI
+// mitigation", arXiv 1701.08197 (SumThreshold Sec. 2.1, SIR Sec. 2.2, history
+// flagger Sec. 4.1; one independent block per station, polarisation and subband,
+// Sec. 4.1 domain decomposition).
+//
+// The host validates every block (all-or-nothing), groups blocks by the kernel
+// variant their time length needs, orders each group by decreasing size so the
+// largest blocks start first, uploads one descriptor table and launches one
+// kernel per group on the caller's stream.  No allocation happens after
+// lof_create: descriptor tables and mask scratch live in a small ring of slots,
+// each slot guarded by an event so that calls on different streams can overlap.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lof.h"
+#include "lof_kernels.hpp"
+
+using lofk::DevBlock;
+using lofk::DevParams;
+
+namespace {
+
+constexpr int NSLOT = 4;
+constexpr int MAX_TIMES = lofk::SIR_SEG * lofk::SIR_MAX_SEGS;   // 262144
+
+thread_local const char* g_create_err = "no error";
+
+struct Slot {
+  DevBlock* d_desc = nullptr;
+  DevBlock* h_desc = nullptr;     // pinned
+  uint64_t* d_mask = nullptr;
+  hipEvent_t ev = nullptr;
+  bool used = false;
+};
+
+int time_class(int T) { return T <= 2048 ? 0 : (T <= 3072 ? 1 : 2); }
+
+size_t elem_size(int dtype) { return dtype == LOF_CI8 ? 2 : (dtype == LOF_F32 ? 4 : 8); }
+
+}  // namespace
+
+struct lof_ctx {
+  lof_params prm;
+  int dev = 0;
+  double* ring = nullptr;
+  int32_t* rcount = nullptr;
+  int32_t* rhead = nullptr;
+  double* pend = nullptr;
+  uint8_t* pvalid = nullptr;
+  Slot slot[NSLOT];
+  int next = 0;
+  size_t mask_words = 0;
+  std::vector<int32_t> seen;     // per stream: last call that named it
+  int32_t call_no = 0;
+  std::vector<DevBlock> tmp;
+  std::vector<int> order;
+  const char* err = "no error";
+};
+
+namespace {
+
+struct DevGuard {
+  int prev = -1;
+  explicit DevGuard(int d) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != d) (void)hipSetDevice(d);
+  }
+  ~DevGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+DevParams dev_params(const lof_ctx* c, uint64_t* mask, void* stats) {
+  DevParams P;
+  P.start = c->prm.start_threshold;
+  P.p = c->prm.p;
+  P.sens = c->prm.sensitivity;
+  P.hs = c->prm.history_sensitivity;
+  P.nl_t = c->prm.n_levels;
+  P.nl_f = c->prm.n_levels_freq < 0 ? c->prm.n_levels : c->prm.n_levels_freq;
+  P.eta_num = c->prm.sir_eta_num;
+  P.eta_den = c->prm.sir_eta_den;
+  P.H = c->prm.history_len;
+  P.Hmin = c->prm.history_min;
+  P.maxC = c->prm.max_channels;
+  P.literal = (c->prm.options & LOF_OPT_LITERAL_HISTORY_TIE) ? 1 : 0;
+  P.ring = c->ring;
+  P.rcount = c->rcount;
+  P.rhead = c->rhead;
+  P.pend = c->pend;
+  P.pvalid = c->pvalid;
+  P.maskw = mask;
+  P.stats = stats;
+  return P;
+}
+
+const char* check_params(const lof_params* p) {
+  if (!p) return "params is NULL";
+  if (!(p->start_threshold == p->start_threshold) || !(p->p == p->p) || !(p->sensitivity == p->sensitivity) ||
+      !(p->history_sensitivity == p->history_sensitivity))
+    return "NaN parameter";
+  if (p->n_levels < 1 || p->n_levels > lofk::ST_MAX_LEVELS) return "n_levels must be in 1..7 (windows up to 64)";
+  if (p->n_levels_freq < -1 || p->n_levels_freq > lofk::ST_MAX_LEVELS) return "n_levels_freq must be -1 or 0..7";
+  if (p->sir_eta_den < 1 || p->sir_eta_den > 1024 || p->sir_eta_num < 0 || p->sir_eta_num > p->sir_eta_den)
+    return "SIR eta must be num/den with 0 <= num <= den <= 1024";
+  if (p->history_len < 1 || p->history_len > 4096) return "history_len must be in 1..4096";
+  if (p->history_min < 0) return "history_min must be >= 0";
+  if (p->max_streams < 1) return "max_streams must be >= 1";
+  if (p->max_channels < 1 || p->max_channels > LOF_MAX_CHANNELS) return "max_channels must be in 1..1024";
+  if (p->max_blocks_per_call < 1) return "max_blocks_per_call must be >= 1";
+  if (p->max_samples_per_call < 1) return "max_samples_per_call must be >= 1";
+  return nullptr;
+}
+
+lof_status fail(lof_ctx* c, lof_status s, const char* msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+lof_status lof_default_params(lof_params* p) {
+  if (!p) return LOF_ERR_INVALID;
+  std::memset(p, 0, sizeof(*p));
+  p->start_threshold = 6.0;
+  p->p = 1.5;
+  p->sensitivity = 1.0;
+  p->n_levels = 7;
+  p->n_levels_freq = -1;
+  p->sir_eta_num = 1;
+  p->sir_eta_den = 5;
+  p->history_sensitivity = 6.0;
+  p->history_len = 32;
+  p->history_min = 4;
+  p->max_streams = 1;
+  p->max_channels = 64;
+  p->max_blocks_per_call = 1;
+  p->max_samples_per_call = LOF_MAX_BLOCK_SAMPLES;
+  p->options = 0;
+  return LOF_OK;
+}
+
+lof_status lof_destroy(lof_ctx* c) {
+  if (!c) return LOF_OK;
+  DevGuard g(c->dev);
+  for (auto& s : c->slot) {
+    if (s.d_desc) (void)hipFree(s.d_desc);
+    if (s.h_desc) (void)hipHostFree(s.h_desc);
+    if (s.d_mask) (void)hipFree(s.d_mask);
+    if (s.ev) (void)hipEventDestroy(s.ev);
+  }
+  if (c->ring) (void)hipFree(c->ring);
+  if (c->rcount) (void)hipFree(c->rcount);
+  if (c->rhead) (void)hipFree(c->rhead);
+  if (c->pend) (void)hipFree(c->pend);
+  if (c->pvalid) (void)hipFree(c->pvalid);
+  delete c;
+  return LOF_OK;
+}
+
+lof_status lof_create(const lof_params* params, int hip_device, lof_ctx** out) {
+  if (!out) {
+    g_create_err = "out is NULL";
+    return LOF_ERR_INVALID;
+  }
+  *out = nullptr;
+  if (const char* m = check_params(params)) {
+    g_create_err = m;
+    return LOF_ERR_INVALID;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) {
+    g_create_err = "no such HIP device";
+    return LOF_ERR_INVALID;
+  }
+  lof_ctx* c = new (std::nothrow) lof_ctx();
+  if (!c) {
+    g_create_err = "host allocation failed";
+    return LOF_ERR_NOMEM;
+  }
+  c->prm = *params;
+  c->dev = hip_device;
+  DevGuard g(hip_device);
+  const int64_t SC = (int64_t)params->max_streams * params->max_channels;
+  bool ok = hipMalloc(&c->ring, sizeof(double) * SC * params->history_len) == hipSuccess &&
+            hipMalloc(&c->rcount, sizeof(int32_t) * SC) == hipSuccess &&
+            hipMalloc(&c->rhead, sizeof(int32_t) * SC) == hipSuccess &&
+            hipMalloc(&c->pend, sizeof(double) * SC) == hipSuccess &&
+            hipMalloc(&c->pvalid, SC) == hipSuccess;
+  if (ok) {
+    ok = hipMemset(c->ring, 0, sizeof(double) * SC * params->history_len) == hipSuccess &&
+         hipMemset(c->rcount, 0, sizeof(int32_t) * SC) == hipSuccess &&
+         hipMemset(c->rhead, 0, sizeof(int32_t) * SC) == hipSuccess &&
+         hipMemset(c->pend, 0, sizeof(double) * SC) == hipSuccess &&
+         hipMemset(c->pvalid, 0, SC) == hipSuccess;
+  }
+  // mask scratch: one u64 word per 64 samples of a row, rows rounded up
+  c->mask_words = (size_t)(params->max_samples_per_call / 64) +
+                  (size_t)params->max_blocks_per_call * (size_t)params->max_channels + 64;
+  for (int i = 0; ok && i < NSLOT; ++i) {
+    Slot& s = c->slot[i];
+    ok = hipMalloc(&s.d_desc, sizeof(DevBlock) * params->max_blocks_per_call) == hipSuccess &&
+         hipHostMalloc(&s.h_desc, sizeof(DevBlock) * params->max_blocks_per_call, hipHostMallocDefault) ==
+             hipSuccess &&
+         hipMalloc(&s.d_mask, sizeof(uint64_t) * c->mask_words) == hipSuccess &&
+         hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) == hipSuccess;
+  }
+  if (ok) ok = hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    lof_destroy(c);
+    g_create_err = "device allocation failed";
+    return LOF_ERR_NOMEM;
+  }
+  c->seen.assign(params->max_streams, -1);
+  c->tmp.resize(params->max_blocks_per_call);
+  c->order.resize(params->max_blocks_per_call);
+  *out = c;
+  return LOF_OK;
+}
+
+lof_status lof_flag_blocks(lof_ctx* c, const lof_block* blocks, int32_t n, void* hip_stream,
+                           lof_block_stats* stats) {
+  if (!c) return LOF_ERR_INVALID;
+  if (n < 0) return fail(c, LOF_ERR_INVALID, "n_blocks < 0");
+  if (n == 0) return LOF_OK;
+  if (!blocks) return fail(c, LOF_ERR_INVALID, "blocks is NULL");
+  if (n > c->prm.max_blocks_per_call) return fail(c, LOF_ERR_CAPACITY, "more blocks than max_blocks_per_call");
+  // ---- validation (all-or-nothing)
+  c->call_no++;
+  if (c->call_no == 0x7fffffff) {
+    std::fill(c->seen.begin(), c->seen.end(), -1);
+    c->call_no = 1;
+  }
+  int64_t samples = 0;
+  size_t words = 0;
+  for (int i = 0; i < n; ++i) {
+    const lof_block& b = blocks[i];
+    if (!b.data || !b.flags) return fail(c, LOF_ERR_INVALID, "block data or flags pointer is NULL");
+    if (b.n_channels < 1 || b.n_times < 1) return fail(c, LOF_ERR_INVALID, "block shape must be >= 1 x 1");
+    if (b.n_channels > LOF_MAX_CHANNELS) return fail(c, LOF_ERR_INVALID, "more than 1024 channels");
+    if (b.n_channels > c->prm.max_channels) return fail(c, LOF_ERR_CAPACITY, "n_channels > max_channels");
+    if (b.n_times > MAX_TIMES) return fail(c, LOF_ERR_INVALID, "more than 262144 times");
+    if ((int64_t)b.n_channels * b.n_times > LOF_MAX_BLOCK_SAMPLES)
+      return fail(c, LOF_ERR_INVALID, "block larger than 2^23 samples");
+    if (b.data_row_stride < b.n_times || b.flag_row_stride < b.n_times)
+      return fail(c, LOF_ERR_INVALID, "row stride smaller than n_times");
+    if (b.dtype < LOF_CI8 || b.dtype > LOF_C64_AMP) return fail(c, LOF_ERR_INVALID, "unknown dtype");
+    if (b.stream_id < -1 || b.stream_id >= c->prm.max_streams)
+      return fail(c, LOF_ERR_INVALID, "stream_id out of range");
+    if (b.stream_id >= 0) {
+      if (c->seen[b.stream_id] == c->call_no) return fail(c, LOF_ERR_INVALID, "stream_id repeated in one call");
+      c->seen[b.stream_id] = c->call_no;
+    }
+    samples += (int64_t)b.n_channels * b.n_times;
+    words += (size_t)b.n_channels * (size_t)((b.n_times + 63) / 64);
+  }
+  if (samples > c->prm.max_samples_per_call) return fail(c, LOF_ERR_CAPACITY, "more samples than max_samples_per_call");
+  if (words > c->mask_words) return fail(c, LOF_ERR_CAPACITY, "mask scratch too small");
+
+  DevGuard g(c->dev);
+  hipStream_t st = (hipStream_t)hip_stream;
+  Slot& s = c->slot[c->next];
+  c->next = (c->next + 1) % NSLOT;
+  if (s.used) {
+    // the slot's previous call must be done before its table and scratch are reused
+    if (hipEventSynchronize(s.ev) != hipSuccess) return fail(c, LOF_ERR_DEVICE, "hipEventSynchronize failed");
+  }
+  // ---- descriptors: kernel variant groups (integer/float x time class), largest first
+  int* order = c->order.data();
+  for (int i = 0; i < n; ++i) order[i] = i;
+  auto variant = [&](int i) {
+    const lof_block& b = blocks[i];
+    return (b.dtype == LOF_CI8 ? 0 : 3) + time_class(b.n_times);
+  };
+  std::sort(order, order + n, [&](int a, int bb) {
+    const int va = variant(a), vb = variant(bb);
+    if (va != vb) return va < vb;
+    const int64_t sa = (int64_t)blocks[a].n_channels * blocks[a].n_times;
+    const int64_t sb = (int64_t)blocks[bb].n_channels * blocks[bb].n_times;
+    if (sa != sb) return sa > sb;
+    return a < bb;
+  });
+  int64_t moff = 0;
+  int counts[6] = {0, 0, 0, 0, 0, 0};
+  for (int j = 0; j < n; ++j) {
+    const int i = order[j];
+    const lof_block& b = blocks[i];
+    DevBlock& d = s.h_desc[j];
+    d.data = b.data;
+    d.flags = b.flags;
+    d.dstride = b.data_row_stride;
+    d.fstride = b.flag_row_stride;
+    d.C = b.n_channels;
+    d.T = b.n_times;
+    d.dtype = b.dtype;
+    d.stream_id = b.stream_id;
+    d.mask_off = moff;
+    d.out_idx = i;
+    const size_t es = elem_size(b.dtype);
+    d.aligned = (((uintptr_t)b.data % 16) == 0 && ((size_t)b.data_row_stride * es) % 16 == 0) ? 1 : 0;
+    d.faligned = (((uintptr_t)b.flags % 16) == 0 && (b.flag_row_stride % 16) == 0) ? 1 : 0;
+    d.pad = 0;
+    moff += (int64_t)b.n_channels * ((b.n_times + 63) / 64);
+    counts[variant(i)]++;
+  }
+  if (hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(DevBlock) * n, hipMemcpyHostToDevice, st) != hipSuccess)
+    return fail(c, LOF_ERR_DEVICE, "descriptor upload failed");
+  const DevParams P = dev_params(c, s.d_mask, stats);
+  int off = 0;
+  for (int v = 0; v < 6; ++v) {
+    const int cnt = counts[v];
+    if (!cnt) continue;
+    const DevBlock* dd = s.d_desc + off;
+    dim3 grid(cnt), blk(lofk::WG);
+    switch (v) {
+      case 0: hipLaunchKernelGGL((lofk::lof_flag_kernel<true, 32>), grid, blk, 0, st, dd, P); break;
+      case 1: hipLaunchKernelGGL((lofk::lof_flag_kernel<true, 48>), grid, blk, 0, st, dd, P); break;
+      case 2: hipLaunchKernelGGL((lofk::lof_flag_kernel<true, 64>), grid, blk, 0, st, dd, P); break;
+      case 3: hipLaunchKernelGGL((lofk::lof_flag_kernel<false, 32>), grid, blk, 0, st, dd, P); break;
+      case 4: hipLaunchKernelGGL((lofk::lof_flag_kernel<false, 48>), grid, blk, 0, st, dd, P); break;
+      default: hipLaunchKernelGGL((lofk::lof_flag_kernel<false, 64>), grid, blk, 0, st, dd, P); break;
+    }
+    off += cnt;
+  }
+  if (c->prm.options & LOF_OPT_AUTOCOMMIT) {
+    hipLaunchKernelGGL(lofk::lof_commit_desc_kernel, dim3(n), dim3(256), 0, st, s.d_desc, n, P);
+  }
+  if (hipGetLastError() != hipSuccess) return fail(c, LOF_ERR_DEVICE, "kernel launch failed");
+  if (hipEventRecord(s.ev, st) != hipSuccess) return fail(c, LOF_ERR_DEVICE, "hipEventRecord failed");
+  s.used = true;
+  return LOF_OK;
+}
+
+lof_status lof_history_update(lof_ctx* c, const int32_t* ids, int32_t n, void* hip_stream) {
+  if (!c) return LOF_ERR_INVALID;
+  if (n < 0) return fail(c, LOF_ERR_INVALID, "n < 0");
+  std::vector<int32_t> list;
+  if (ids) {
+    list.assign(ids, ids + n);
+    for (int32_t s : list)
+      if (s < 0 || s >= c->prm.max_streams) return fail(c, LOF_ERR_INVALID, "stream id out of range");
+    std::sort(list.begin(), list.end());
+    list.erase(std::unique(list.begin(), list.end()), list.end());
+    if (list.empty()) return LOF_OK;
+  }
+  DevGuard g(c->dev);
+  hipStream_t st = (hipStream_t)hip_stream;
+  const DevParams P = dev_params(c, nullptr, nullptr);
+  const int TPB = 256;
+  if (!ids) {
+    lofk::IdList none;
+    none.n = 0;
+    const int64_t tot = (int64_t)c->prm.max_streams * c->prm.max_channels;
+    hipLaunchKernelGGL(lofk::lof_commit_kernel, dim3((unsigned)((tot + TPB - 1) / TPB)), dim3(TPB), 0, st, none,
+                       c->prm.max_streams, P);
+  } else {
+    for (size_t i = 0; i < list.size(); i += 255) {
+      lofk::IdList L;
+      L.n = (int32_t)std::min<size_t>(255, list.size() - i);
+      for (int j = 0; j < L.n; ++j) L.ids[j] = list[i + j];
+      const int64_t tot = (int64_t)L.n * c->prm.max_channels;
+      hipLaunchKernelGGL(lofk::lof_commit_kernel, dim3((unsigned)((tot + TPB - 1) / TPB)), dim3(TPB), 0, st, L, 0,
+                         P);
+    }
+  }
+  if (hipGetLastError() != hipSuccess) return fail(c, LOF_ERR_DEVICE, "commit launch failed");
+  return LOF_OK;
+}
+
+lof_status lof_history_export(lof_ctx* c, double* values, int32_t* counts, double* staged, uint8_t* staged_valid,
+                              void* hip_stream) {
+  if (!c) return LOF_ERR_INVALID;
+  DevGuard g(c->dev);
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int64_t SC = (int64_t)c->prm.max_streams * c->prm.max_channels;
+  const int H = c->prm.history_len;
+  std::vector<double> ring((size_t)SC * H);
+  std::vector<int32_t> cnt(SC), head(SC);
+  bool ok = hipMemcpyAsync(ring.data(), c->ring, sizeof(double) * SC * H, hipMemcpyDeviceToHost, st) == hipSuccess &&
+            hipMemcpyAsync(cnt.data(), c->rcount, sizeof(int32_t) * SC, hipMemcpyDeviceToHost, st) == hipSuccess &&
+            hipMemcpyAsync(head.data(), c->rhead, sizeof(int32_t) * SC, hipMemcpyDeviceToHost, st) == hipSuccess;
+  if (ok && staged) ok = hipMemcpyAsync(staged, c->pend, sizeof(double) * SC, hipMemcpyDeviceToHost, st) == hipSuccess;
+  if (ok && staged_valid)
+    ok = hipMemcpyAsync(staged_valid, c->pvalid, SC, hipMemcpyDeviceToHost, st) == hipSuccess;
+  if (ok) ok = hipStreamSynchronize(st) == hipSuccess;
+  if (!ok) return fail(c, LOF_ERR_DEVICE, "history export copy failed");
+  for (int64_t i = 0; i < SC; ++i) {
+    if (counts) counts[i] = cnt[i];
+    if (values) {
+      for (int j = 0; j < H; ++j) {
+        double v = 0.0;
+        if (j < cnt[i]) {
+          int k = head[i] - cnt[i] + j;
+          if (k < 0) k += H;
+          v = ring[(size_t)i * H + k];
+        }
+        values[(size_t)i * H + j] = v;
+      }
+    }
+  }
+  return LOF_OK;
+}
+
+const char* lof_last_error(const lof_ctx* c) { return c ? c->err : g_create_err; }
+
+}  // extern "C"

@@ -1,0 +1,1010 @@
+// lof_kernels.hpp -- the per-block phases of the LOF flagging kernel (gfx950).
+// See lof_device.hpp for the layouts.  Citations are to van Nieuwpoort,
+// "Towards exascale real-time RFI mitigation", arXiv 1701.08197.
+#pragma once
+#include "lof_device.hpp"
+
+namespace lofk {
+
+// ===================================================================== phase A
+// Block median and population standard deviation over all C*T samples
+// (Sec. 2.1 threshold definition; Sec. 4.2 asks for an O(N) median): one pass
+// accumulates exact (integer input) or float64 moments and the top 12-bit digit
+// histogram of an order-preserving 32-bit key; further passes refine the digit
+// of the two middle order statistics.  Then the thresholds of Sec. 2.1.
+
+// block-wide: bin holding `rank` (0-based) in the 4096-bin histogram h
+__device__ void find_bin(const uint32_t* h, uint32_t rank, Smem& sm, uint32_t& bin, uint32_t& rem) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int PER = HBINS / WG;
+  uint32_t loc[PER];
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    loc[j] = h[tid * PER + j];
+    s += loc[j];
+  }
+  uint32_t x = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) sm.scan[wv] = x;
+  __syncthreads();
+  uint32_t off = 0;
+  for (int w = 0; w < wv; ++w) off += sm.scan[w];
+  const uint32_t excl = off + x - s;
+  if (rank >= excl && rank < excl + s) {
+    uint32_t c = excl;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      if (rank < c + loc[j]) {
+        sm.sel[0] = (uint32_t)(tid * PER + j);
+        sm.sel[1] = rank - c;
+        break;
+      }
+      c += loc[j];
+    }
+  }
+  __syncthreads();
+  bin = sm.sel[0];
+  rem = sm.sel[1];
+  __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t fkey(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float fkey_inv(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k ^ 0x80000000u) : ~k);
+}
+
+template <bool INT>
+__device__ void phase_stats(const DevBlock& b, const DevParams& P, Smem& sm) {
+  typedef typename PowT<INT>::T VT;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nch = (b.T + 7) >> 3;
+  const int64_t items = (int64_t)b.C * nch;
+  const int64_t N = (int64_t)b.C * b.T;
+  const int KB = INT ? 16 : 32;  // key bits (integer power <= 32768 < 2^16)
+  const int npass = INT ? 2 : 3;
+  const int dbits[3] = {12, INT ? 4 : 12, 8};
+
+  for (int i = tid; i < 2 * HBINS; i += WG) (&sm.u.hist[0][0])[i] = 0u;
+  __syncthreads();
+
+  unsigned long long s1u = 0, s2u = 0;
+  double s1d = 0.0, s2d = 0.0;
+  {
+    const int lo = KB - 12;
+    for (int64_t it = tid; it < items; it += WG) {
+      const int row = (int)(it / nch);
+      const int t0 = (int)(it - (int64_t)row * nch) * 8;
+      VT v[8];
+      const int nv = load8<INT>(b, row, t0, v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (j < nv) {
+          uint32_t key;
+          if (INT) {
+            const uint32_t p = (uint32_t)v[j];
+            s1u += p;
+            s2u += (unsigned long long)p * p;
+            key = p;
+          } else {
+            const double d = (double)v[j];
+            s1d += d;
+            s2d += d * d;
+            key = fkey((float)v[j]);
+          }
+          atomicAdd(&sm.u.hist[0][key >> lo], 1u);
+        }
+      }
+    }
+  }
+  // block reduction of the moments (fixed order: deterministic)
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    s1u += __shfl_xor(s1u, d);
+    s2u += __shfl_xor(s2u, d);
+    s1d += __shfl_xor(s1d, d);
+    s2d += __shfl_xor(s2d, d);
+  }
+  if (lane == 0) {
+    sm.red_u[0][wv] = s1u;
+    sm.red_u[1][wv] = s2u;
+    sm.red_d[0][wv] = s1d;
+    sm.red_d[1][wv] = s2d;
+  }
+  __syncthreads();
+
+  // radix select of ranks (N-1)/2 and N/2
+  uint32_t r0 = (uint32_t)((N - 1) / 2), r1 = (uint32_t)(N / 2);
+  uint32_t pre0 = 0, pre1 = 0;
+  int hi = KB;
+  for (int pass = 0; pass < npass; ++pass) {
+    const int db = dbits[pass];
+    const int lo = hi - db;
+    const uint32_t dmask = (1u << db) - 1u;
+    if (pass > 0) {
+      for (int i = tid; i < 2 * HBINS; i += WG) (&sm.u.hist[0][0])[i] = 0u;
+      __syncthreads();
+      const bool two = pre1 != pre0;
+      for (int64_t it = tid; it < items; it += WG) {
+        const int row = (int)(it / nch);
+        const int t0 = (int)(it - (int64_t)row * nch) * 8;
+        VT v[8];
+        const int nv = load8<INT>(b, row, t0, v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          if (j < nv) {
+            const uint32_t key = INT ? (uint32_t)v[j] : fkey((float)v[j]);
+            const uint32_t top = key >> hi;
+            const uint32_t dg = (key >> lo) & dmask;
+            if (top == pre0) atomicAdd(&sm.u.hist[0][dg], 1u);
+            if (two && top == pre1) atomicAdd(&sm.u.hist[1][dg], 1u);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    uint32_t b0, q0, b1, q1;
+    const bool two = pass > 0 && pre1 != pre0;
+    find_bin(sm.u.hist[0], r0, sm, b0, q0);
+    find_bin(two ? sm.u.hist[1] : sm.u.hist[0], r1, sm, b1, q1);
+    pre0 = (pre0 << db) | b0;
+    pre1 = (pre1 << db) | b1;
+    r0 = q0;
+    r1 = q1;
+    hi = lo;
+  }
+
+  if (tid == 0) {
+    unsigned long long S1u = 0, S2u = 0;
+    double S1d = 0.0, S2d = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      S1u += sm.red_u[0][w];
+      S2u += sm.red_u[1][w];
+      S1d += sm.red_d[0][w];
+      S2d += sm.red_d[1][w];
+    }
+    double v0, v1;
+    if (INT) {
+      v0 = (double)pre0;
+      v1 = (double)pre1;
+    } else {
+      v0 = (double)fkey_inv(pre0);
+      v1 = (double)fkey_inv(pre1);
+    }
+    const double med = (N & 1) ? v0 : (v0 + v1) / 2.0;
+    const double n = (double)N;
+    double mu, ex2;
+    if (INT) {
+      mu = (double)S1u / n;     // S1, S2 < 2^53: exact conversions
+      ex2 = (double)S2u / n;
+    } else {
+      mu = S1d / n;
+      ex2 = S2d / n;
+    }
+    double var = ex2 - mu * mu;
+    if (var < 0.0) var = 0.0;
+    const double sd = __builtin_sqrt(var);
+    sm.median = med;
+    sm.sigma = sd;
+    const int nT = max(P.nl_t, P.nl_f);
+    double pk = 1.0;
+    for (int k = 0; k < 16; ++k) {
+      if (k < nT) {
+        const double f = P.start * pk / (double)(1 << k);
+        sm.T[k] = med + sd * (f * P.sens);
+        sm.Tf[k] = (float)sm.T[k];
+        pk = pk * P.p;
+      } else {
+        sm.T[k] = 0.0;
+        sm.Tf[k] = 0.0f;
+      }
+    }
+  }
+  __syncthreads();
+  if (INT) {
+    // exact integer window thresholds: flag iff S > floor(c * T_k); stored packed
+    // against the window word D = S*512 + 4c as G = floor(c*T_k)*512 + 511.
+    for (int i = tid; i < ST_MAX_LEVELS * 128; i += WG) {
+      const int k = i >> 7, c = i & 127;
+      const double T = sm.T[k];
+      const double cd = (double)c;
+      const double prod = cd * T;
+      const double err = __builtin_fma(cd, T, -prod);
+      double fl = __builtin_floor(prod);
+      if (prod == fl && err < 0.0) fl -= 1.0;
+      int32_t g;
+      if (fl >= 4194303.0) g = 0x7fffffff;
+      else if (fl < -2097152.0) g = -2097152 * 512 + 511;
+      else g = (int32_t)fl * 512 + 511;
+      sm.G[k][c] = g;
+    }
+  }
+  __syncthreads();
+}
+
+// ===================================================================== SumThreshold core
+// One-dimensional SumThreshold (Sec. 2.1) over a sequence of n positions held by
+// a group of lanes (L per lane, lane_in_group = lig).  Levels are synchronous:
+// every window of level k is judged on the mask after level k-1; flagged samples
+// are left out of the window's sum and count; a window whose unflagged mean
+// exceeds T_k flags all its samples.  Only full windows (s + I <= n) are judged.
+//
+// Integer input: v = p*512 + 4 for an unflagged sample, 0 for a flagged one, so a
+// window word D = S*512 + 4c packs the exact unflagged sum S and count c; the test
+// S > floor(c*T_k) is D > G_k[c].  Float input: float32 sums and counts, test
+// S > c*T_k in float32.
+
+template <int L, int H, class VT>
+__device__ __forceinline__ void dbl_step(VT (&D)[L]) {
+  static_assert(H <= L, "window half must fit in one lane");
+  VT nb[H];
+#pragma unroll
+  for (int m = 0; m < H; ++m) nb[m] = shl1(D[m]);
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const VT o = (i + H < L) ? D[(i + H < L) ? i + H : 0] : nb[(i + H >= L) ? i + H - L : 0];
+    D[i] = D[i] + o;
+  }
+}
+
+template <int L, class VT>
+__device__ __forceinline__ void dbl_h(VT (&D)[L], int h) {
+  switch (h) {
+    case 1: dbl_step<L, 1>(D); break;
+    case 2: dbl_step<L, 2>(D); break;
+    case 4: dbl_step<L, 4>(D); break;
+    case 8: dbl_step<L, 8>(D); break;
+    case 16: if constexpr (L >= 16) dbl_step<L, 16>(D); break;
+    case 32: if constexpr (L >= 32) dbl_step<L, 32>(D); break;
+    default: break;
+  }
+}
+
+// window-start bits wf (bit i <-> start lig*L+i) -> flagged positions of this lane:
+// OR over starts s in [j-I+1, j], with starts of up to two lanes to the left.
+template <int L>
+__device__ __forceinline__ uint64_t spread(uint64_t wf, int lig, int I) {
+  uint64_t p1 = shr1_64(wf);
+  uint64_t p2 = 0;
+  if (L < 64) p2 = shr1_64(p1);
+  if (lig == 0) p1 = 0;
+  if (lig <= 1) p2 = 0;
+  uint64_t xlo;
+  if (L == 64) xlo = p1;
+  else if (L == 48) xlo = (p1 << 16) | (p2 >> 32);
+  else if (L == 32) xlo = (p1 << 32) | p2;
+  else xlo = 0;  // L < 32 only with groups of one lane
+  uint64_t xhi = wf;
+  for (int d = 1; d < I; d <<= 1) {
+    xhi |= (xhi << d) | (xlo >> (64 - d));
+    xlo |= xlo << d;
+  }
+  return xhi;
+}
+
+// Loader interface: fill(fm, D, N) sets D (and N, float path) to the level-0
+// window values of the lane's L positions under mask fm.
+template <bool INT, int L, class LD>
+__device__ uint64_t st_core(LD& ld, uint64_t fm, const int lig, const int n, const int kfirst,
+                            const int nlev, const Smem& sm) {
+  typedef typename PowT<INT>::T VT;
+  VT D[L];
+  float Nc[L];
+  const int pos0 = lig * L;
+  const int nval = clampi(n - pos0, 0, L);
+  const uint64_t vmask = lowmask(nval);
+  ld.fill(fm, D, Nc);
+  bool dirty = false;
+  for (int k = kfirst; k < nlev; ++k) {
+    const int I = 1 << k;
+    if (I > n) break;
+    if (k > 0) {
+      if (dirty) {
+        ld.fill(fm, D, Nc);
+        for (int j = 0; j + 1 < k; ++j) {
+          dbl_h<L>(D, 1 << j);
+          if constexpr (!INT) dbl_h<L>(Nc, 1 << j);
+        }
+      }
+      dbl_h<L>(D, I >> 1);
+      if constexpr (!INT) dbl_h<L>(Nc, I >> 1);
+    }
+    // judge the windows of this level
+    uint32_t lo = 0, hi = 0;
+    if (INT) {
+      const int32_t* Gk = sm.G[k];
+      const bool clean = __ballot(fm != 0) == 0;
+      if (k == 0 && clean) {
+        const int32_t g = Gk[1];
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+          const uint32_t h = ((int32_t)(uint32_t)D[i] > g) ? 1u : 0u;
+          if (i < 32) lo |= h << i; else hi |= h << (i - 32);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+          const uint32_t d = (uint32_t)D[i];
+          const uint32_t h = ((int32_t)d > Gk[(d >> 2) & 127u]) ? 1u : 0u;
+          if (i < 32) lo |= h << i; else hi |= h << (i - 32);
+        }
+      }
+    } else {
+      const float Tk = sm.Tf[k];
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        const float c = Nc[i];
+        const uint32_t h = (c > 0.0f && (float)D[i] > c * Tk) ? 1u : 0u;
+        if (i < 32) lo |= h << i; else hi |= h << (i - 32);
+      }
+    }
+    uint64_t wf = (uint64_t)lo | ((uint64_t)hi << 32);
+    wf &= lowmask(n - I + 1 - pos0) & vmask;
+    if (__ballot(wf != 0) == 0) {
+      dirty = false;
+      continue;
+    }
+    const uint64_t nb = spread<L>(wf, lig, I) & vmask;
+    const uint64_t changed = nb & ~fm;
+    fm |= nb;
+    dirty = __ballot(changed != 0) != 0;
+  }
+  return fm;
+}
+
+// ---- loaders
+template <bool INT, int L>
+struct TimeLoader {
+  const DevBlock* b;
+  int row, q, nval;   // q: absolute time of the lane's first position
+  bool ok;
+  __device__ __forceinline__ void fill(uint64_t fm, typename PowT<INT>::T (&D)[L], float (&Nc)[L]) {
+    if (INT) {
+      const uint8_t* rb = (const uint8_t*)b->data + ((int64_t)row * b->dstride + q) * 2;
+      uint32_t p[L];
+      if (ok && nval == L && b->aligned) {
+#pragma unroll
+        for (int j = 0; j < L / 8; ++j) {
+          const uint4 w = *(const uint4*)(rb + 16 * j);
+          const uint32_t a[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            p[8 * j + 2 * m] = ci8_power(a[m] & 0xffffu);
+            p[8 * j + 2 * m + 1] = ci8_power(a[m] >> 16);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < L; ++i)
+          p[i] = (ok && i < nval) ? ci8_power(*(const uint16_t*)(rb + 2 * i)) : 0u;
+      }
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        const bool live = i < nval && ok && !((fm >> i) & 1ull);
+        D[i] = (typename PowT<INT>::T)(live ? p[i] * 512u + 4u : 0u);
+      }
+    } else {
+      float p[L];
+      if (b->dtype == 2) {
+        const float* rb = (const float*)b->data + (int64_t)row * b->dstride + q;
+        if (ok && nval == L && b->aligned) {
+#pragma unroll
+          for (int j = 0; j < L / 4; ++j) {
+            const float4 w = *(const float4*)(rb + 4 * j);
+            p[4 * j] = w.x; p[4 * j + 1] = w.y; p[4 * j + 2] = w.z; p[4 * j + 3] = w.w;
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < L; ++i) p[i] = (ok && i < nval) ? rb[i] : 0.0f;
+        }
+      } else {
+        const float2* rb = (const float2*)b->data + (int64_t)row * b->dstride + q;
+        const bool amp = b->dtype == 3;
+        if (ok && nval == L && b->aligned) {
+#pragma unroll
+          for (int j = 0; j < L / 2; ++j) {
+            const float4 w = *(const float4*)(rb + 2 * j);
+            p[2 * j] = amp ? c64_amp(w.x, w.y) : c64_power(w.x, w.y);
+            p[2 * j + 1] = amp ? c64_amp(w.z, w.w) : c64_power(w.z, w.w);
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < L; ++i) {
+            float r = 0.0f;
+            if (ok && i < nval) {
+              const float2 z = rb[i];
+              r = amp ? c64_amp(z.x, z.y) : c64_power(z.x, z.y);
+            }
+            p[i] = r;
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        const bool live = i < nval && ok && !((fm >> i) & 1ull);
+        D[i] = (typename PowT<INT>::T)(live ? p[i] : 0.0f);
+        Nc[i] = live ? 1.0f : 0.0f;
+      }
+    }
+  }
+};
+
+template <bool INT, int L>
+struct FreqLoader {
+  const DevBlock* b;
+  int t, ch0, nval;   // column, first channel of the lane, valid channels in lane
+  bool ok;            // t < T
+  __device__ __forceinline__ void fill(uint64_t fm, typename PowT<INT>::T (&D)[L], float (&Nc)[L]) {
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const bool valid = ok && i < nval;
+      const bool live = valid && !((fm >> i) & 1ull);
+      if (INT) {
+        const uint32_t p = valid ? ipower_at(*b, ch0 + i, t) : 0u;
+        D[i] = (typename PowT<INT>::T)(live ? p * 512u + 4u : 0u);
+      } else {
+        const float p = valid ? fpower_at(*b, ch0 + i, t) : 0.0f;
+        D[i] = (typename PowT<INT>::T)(live ? p : 0.0f);
+        Nc[i] = live ? 1.0f : 0.0f;
+      }
+    }
+  }
+};
+
+// ---- bit output of a row layout (lane bits at lig*L) into u64 row words
+template <int L>
+__device__ __forceinline__ void write_row_bits(uint64_t* rowp, int W, uint64_t fm, int lig, int G, bool ok) {
+  if (L == 64) {
+    if (ok && lig < W) rowp[lig] = fm;
+  } else if (L == 32) {
+    const uint64_t nx = shl1_64(fm);
+    if (G == 1) {
+      if (ok) rowp[0] = fm;
+    } else if ((lig & 1) == 0) {
+      if (ok && (lig >> 1) < W) rowp[lig >> 1] = fm | (nx << 32);
+    }
+  } else if (L == 48) {
+    const uint64_t nx = quad_next_64(fm);
+    const int j = lig & 3;
+    if (j < 3) {
+      const uint64_t word = (fm >> (16 * j)) | (nx << (48 - 16 * j));
+      const int widx = (lig >> 2) * 3 + j;
+      if (ok && widx < W) rowp[widx] = word;
+    }
+  } else {
+    if (ok && G == 1) rowp[0] = fm;   // L < 32: one lane per row
+  }
+}
+
+__device__ __forceinline__ uint64_t get_bits(const uint64_t* rowp, int W, int q, int L) {
+  const int w = q >> 6, o = q & 63;
+  uint64_t r = (w < W) ? (ld_mask(rowp + w) >> o) : 0ull;
+  if (o != 0 && o + L > 64 && w + 1 < W) r |= ld_mask(rowp + w + 1) << (64 - o);
+  return r & lowmask(L);
+}
+
+// ===================================================================== phase B
+template <bool INT, int L>
+__device__ void phase_time(const DevBlock& b, const DevParams& P, Smem& sm) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int T = b.T, C = b.C;
+  const int W = (T + 63) >> 6;
+  uint64_t* m0 = P.maskw + b.mask_off;
+  const int nlev = min(P.nl_t, ST_MAX_LEVELS);
+  if (T <= 64 * L) {
+    int G = 1;
+    while (G * L < T) G <<= 1;
+    const int R = 64 / G, lig = lane & (G - 1), grp = lane / G;
+    for (int rb = wv * R; rb < C; rb += NW * R) {
+      const int row = rb + grp;
+      const bool ok = row < C;
+      TimeLoader<INT, L> ld{&b, ok ? row : 0, lig * L, clampi(T - lig * L, 0, L), ok};
+      const uint64_t fm = st_core<INT, L>(ld, 0ull, lig, T, 0, nlev, sm);
+      write_row_bits<L>(m0 + (int64_t)(ok ? row : 0) * W, W, fm, lig, G, ok);
+    }
+  } else {
+    // long rows: segments of 64*L positions, SEG_CORE finished positions each
+    for (int row = wv; row < C; row += NW) {
+      for (int c0 = 0; c0 < T; c0 += SEG_CORE) {
+        const int c1 = min(T, c0 + SEG_CORE);
+        const int q0 = max(0, c0 - SEG_HALO);
+        const int n = min(T, q0 + 64 * L) - q0;
+        TimeLoader<INT, L> ld{&b, row, q0 + lane * L, clampi(n - lane * L, 0, L), true};
+        const uint64_t fm = st_core<INT, L>(ld, 0ull, lane, n, 0, nlev, sm);
+        const int pos = q0 + lane * L;   // L == 64: one word per lane
+        if (L == 64 && pos >= c0 && pos < c1) m0[(int64_t)row * W + (pos >> 6)] = fm;
+      }
+    }
+  }
+}
+
+// frequency SumThreshold (Sec. 2.1, the other direction), starting from the time mask
+template <bool INT, int LF>
+__device__ void phase_freq_l(const DevBlock& b, const DevParams& P, Smem& sm, int G) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int T = b.T, C = b.C;
+  const int W = (T + 63) >> 6;
+  uint64_t* m0 = P.maskw + b.mask_off;
+  const int nlev = min(P.nl_f, ST_MAX_LEVELS);
+  const int CPW = 64 / G;                 // columns per wave pass
+  const int lig = lane & (G - 1), col = lane / G;
+  const int ch0 = lig * LF;
+  const int nval = clampi(C - ch0, 0, LF);
+  for (int tb = wv * CPW; tb < T; tb += NW * CPW) {
+    const int t = tb + col;
+    const bool ok = t < T;
+    const int tw = (ok ? t : 0) >> 6;
+    const int tb_ = (ok ? t : 0) & 63;
+    uint64_t fm0 = 0;
+#pragma unroll 4
+    for (int i = 0; i < LF; ++i) {
+      if (i < nval) {
+        const uint64_t w = ld_mask(m0 + (int64_t)(ch0 + i) * W + tw);
+        fm0 |= ((w >> tb_) & 1ull) << i;
+      }
+    }
+    if (!ok) fm0 = 0;
+    FreqLoader<INT, LF> ld{&b, ok ? t : 0, ch0, nval, ok};
+    const uint64_t fm = st_core<INT, LF>(ld, fm0, lig, C, 1, nlev, sm);
+    uint64_t nb = ok ? (fm & ~fm0) : 0ull;
+    if (G == 1) {
+      // 64 consecutive columns of one word per channel: ballot per channel
+      if (__ballot(nb != 0) != 0) {
+        for (int i = 0; i < LF && i < C; ++i) {
+          const uint64_t word = __ballot((int)((nb >> i) & 1ull));
+          if (word != 0 && lane == 0) or_mask(m0 + (int64_t)i * W + (tb >> 6), word);
+        }
+      }
+    } else {
+      while (nb) {
+        const int i = __builtin_ctzll(nb);
+        nb &= nb - 1;
+        or_mask(m0 + (int64_t)(ch0 + i) * W + tw, 1ull << tb_);
+      }
+    }
+  }
+}
+
+template <bool INT>
+__device__ void phase_freq(const DevBlock& b, const DevParams& P, Smem& sm) {
+  const int C = b.C;
+  if (C <= 1 || P.nl_f <= 1) return;
+  if (C <= 16) phase_freq_l<INT, 16>(b, P, sm, 1);
+  else if (C <= 32) phase_freq_l<INT, 32>(b, P, sm, 1);
+  else {
+    int G = 1;
+    while (G * 64 < C) G <<= 1;
+    phase_freq_l<INT, 64>(b, P, sm, G);
+  }
+}
+
+// ===================================================================== phase C: SIR
+// Scale-invariant rank operator (Sec. 2.2), linear form: weights num (flagged) /
+// num-den (unflagged), W = running sum; y is flagged iff
+// max_{b > y} W[b] - min_{a <= y} W[a] >= 0.  Lanes of a group hold consecutive
+// positions; segment carries chain long rows.
+
+struct SirSum {
+  int tot, mn, mx;   // lane: sum, min of W before each position, max of W after each
+};
+
+template <int L>
+__device__ __forceinline__ SirSum sir_lane_summary(uint64_t bits, int nval, int num, int den) {
+  int W = 0, mn = BIG, mx = -BIG;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    mn = min(mn, W);
+    const int w = (i < nval) ? (((bits >> i) & 1ull) ? num : num - den) : 0;
+    W += w;
+    mx = max(mx, W);
+  }
+  return SirSum{W, mn, mx};
+}
+
+// group scans: base = exclusive sum, pmin = min over earlier lanes of (base+mn),
+// smax = max over later lanes of (base+mx)
+__device__ __forceinline__ void sir_group_scan(const SirSum s, int lig, int G, int& base, int& pmin, int& smax,
+                                               int& gtot, int& gmn, int& gmx) {
+  int x = s.tot;
+  for (int d = 1; d < G; d <<= 1) {
+    const int y = __shfl_up(x, d, G);
+    if (lig >= d) x += y;
+  }
+  base = x - s.tot;
+  gtot = __shfl(x, G - 1, G);
+  int a = base + s.mn;
+  for (int d = 1; d < G; d <<= 1) {
+    const int y = __shfl_up(a, d, G);
+    if (lig >= d) a = min(a, y);
+  }
+  gmn = __shfl(a, G - 1, G);
+  int pa = __shfl_up(a, 1, G);
+  pmin = (lig == 0) ? BIG : pa;
+  int c = base + s.mx;
+  for (int d = 1; d < G; d <<= 1) {
+    const int y = __shfl_down(c, d, G);
+    if (lig + d < G) c = max(c, y);
+  }
+  gmx = __shfl(c, 0, G);
+  int nc = __shfl_down(c, 1, G);
+  smax = (lig == G - 1) ? -BIG : nc;
+}
+
+template <int L>
+__device__ __forceinline__ uint64_t sir_lane_apply(uint64_t bits, int nval, int num, int den, int Wstart,
+                                                   int pmin_in, int smax_in) {
+  int PM[L];
+  int W = Wstart, pm = pmin_in;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    pm = min(pm, W);
+    PM[i] = pm;
+    W += (i < nval) ? (((bits >> i) & 1ull) ? num : num - den) : 0;
+  }
+  int sm = smax_in;
+  uint64_t out = 0;
+#pragma unroll
+  for (int i = L - 1; i >= 0; --i) {
+    sm = max(sm, W);
+    if (sm - PM[i] >= 0) out |= 1ull << i;
+    W -= (i < nval) ? (((bits >> i) & 1ull) ? num : num - den) : 0;
+  }
+  return out & lowmask(nval);
+}
+
+template <int L>
+__device__ void phase_sir_time(const DevBlock& b, const DevParams& P, Smem& sm) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int T = b.T, C = b.C;
+  const int W = (T + 63) >> 6;
+  uint64_t* m0 = P.maskw + b.mask_off;
+  const int num = P.eta_num, den = P.eta_den;
+  if (T <= 64 * L) {
+    int G = 1;
+    while (G * L < T) G <<= 1;
+    const int R = 64 / G, lig = lane & (G - 1), grp = lane / G;
+    for (int rb = wv * R; rb < C; rb += NW * R) {
+      const int row = rb + grp;
+      const bool ok = row < C;
+      uint64_t* rp = m0 + (int64_t)(ok ? row : 0) * W;
+      const int nval = ok ? clampi(T - lig * L, 0, L) : 0;
+      const uint64_t bits = ok ? (get_bits(rp, W, lig * L, L) & lowmask(nval)) : 0ull;
+      const bool any = __ballot(bits != 0) != 0;
+      if (!any && num < den) continue;
+      const SirSum s = sir_lane_summary<L>(bits, nval, num, den);
+      int base, pmin, smax, gt, gn, gx;
+      sir_group_scan(s, lig, G, base, pmin, smax, gt, gn, gx);
+      const uint64_t out = sir_lane_apply<L>(bits, nval, num, den, base, pmin, smax);
+      write_row_bits<L>(rp, W, out, lig, G, ok);
+    }
+  } else {
+    // long rows (L == 64): SIR_SEG positions per segment, two passes with carries
+    const int nseg = (T + SIR_SEG - 1) / SIR_SEG;
+    int(*seg)[3] = sm.u.c.seg[wv];
+    for (int row = wv; row < C; row += NW) {
+      uint64_t* rp = m0 + (int64_t)row * W;
+      bool any = false;
+      for (int s = 0; s < nseg; ++s) {
+        const int q = s * SIR_SEG + lane * L;
+        const int nval = clampi(T - q, 0, L);
+        const uint64_t bits = get_bits(rp, W, q, L) & lowmask(nval);
+        any = any || (__ballot(bits != 0) != 0);
+        const SirSum ss = sir_lane_summary<L>(bits, nval, num, den);
+        int base, pmin, smax, gt, gn, gx;
+        sir_group_scan(ss, lane, 64, base, pmin, smax, gt, gn, gx);
+        if (lane == 0) {
+          seg[s][0] = gt;
+          seg[s][1] = gn;
+          seg[s][2] = gx;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (!any && num < den) continue;
+      // carries: lane s <-> segment s
+      SirSum cs{0, BIG, -BIG};
+      if (lane < nseg) cs = SirSum{seg[lane][0], seg[lane][1], seg[lane][2]};
+      int base, pmin, smax, gt, gn, gx;
+      sir_group_scan(cs, lane, 64, base, pmin, smax, gt, gn, gx);
+      __builtin_amdgcn_wave_barrier();
+      if (lane < nseg) {
+        seg[lane][0] = base;
+        seg[lane][1] = pmin;
+        seg[lane][2] = smax;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int s = 0; s < nseg; ++s) {
+        const int q = s * SIR_SEG + lane * L;
+        const int nval = clampi(T - q, 0, L);
+        const uint64_t bits = get_bits(rp, W, q, L) & lowmask(nval);
+        const SirSum ss = sir_lane_summary<L>(bits, nval, num, den);
+        int lb, lp, lx, a1, a2, a3;
+        sir_group_scan(ss, lane, 64, lb, lp, lx, a1, a2, a3);
+        const int sb = seg[s][0], sp = seg[s][1], sx = seg[s][2];
+        const int pmin_in = min(sp, lp == BIG ? BIG : sb + lp);
+        const int smax_in = max(sx, lx == -BIG ? -BIG : sb + lx);
+        const uint64_t out = sir_lane_apply<L>(bits, nval, num, den, sb + lb, pmin_in, smax_in);
+        // segments are word aligned: every lane owns one word (L == 64)
+        if (nval > 0) rp[q >> 6] = out;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+}
+
+template <int LF>
+__device__ void phase_sir_freq_l(const DevBlock& b, const DevParams& P, Smem& sm, int G) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int T = b.T, C = b.C;
+  const int W = (T + 63) >> 6;
+  uint64_t* m0 = P.maskw + b.mask_off;
+  const int num = P.eta_num, den = P.eta_den;
+  const int CPW = 64 / G;
+  const int lig = lane & (G - 1), col = lane / G;
+  const int ch0 = lig * LF;
+  const int nval = clampi(C - ch0, 0, LF);
+  for (int tb = wv * CPW; tb < T; tb += NW * CPW) {
+    const int t = tb + col;
+    const bool ok = t < T;
+    const int tw = (ok ? t : 0) >> 6;
+    const int tb_ = (ok ? t : 0) & 63;
+    uint64_t bits = 0;
+#pragma unroll 4
+    for (int i = 0; i < LF; ++i) {
+      if (i < nval) {
+        const uint64_t w = ld_mask(m0 + (int64_t)(ch0 + i) * W + tw);
+        bits |= ((w >> tb_) & 1ull) << i;
+      }
+    }
+    if (!ok) bits = 0;
+    if (__ballot(bits != 0) == 0 && num < den) continue;
+    const int nv = ok ? nval : 0;
+    const SirSum s = sir_lane_summary<LF>(bits, nv, num, den);
+    int base = 0, pmin = BIG, smax = -BIG, gt, gn, gx;
+    if (G > 1) sir_group_scan(s, lig, G, base, pmin, smax, gt, gn, gx);
+    const uint64_t out = sir_lane_apply<LF>(bits, nv, num, den, base, pmin, smax);
+    uint64_t nb = out & ~bits;
+    if (G == 1) {
+      if (__ballot(nb != 0) != 0) {
+        for (int i = 0; i < LF && i < C; ++i) {
+          const uint64_t word = __ballot((int)((nb >> i) & 1ull));
+          if (word != 0 && lane == 0) or_mask(m0 + (int64_t)i * W + (tb >> 6), word);
+        }
+      }
+    } else {
+      while (nb) {
+        const int i = __builtin_ctzll(nb);
+        nb &= nb - 1;
+        or_mask(m0 + (int64_t)(ch0 + i) * W + tw, 1ull << tb_);
+      }
+    }
+  }
+}
+
+__device__ void phase_sir_freq(const DevBlock& b, const DevParams& P, Smem& sm) {
+  const int C = b.C;
+  if (C <= 1) return;
+  if (C <= 16) phase_sir_freq_l<16>(b, P, sm, 1);
+  else if (C <= 32) phase_sir_freq_l<32>(b, P, sm, 1);
+  else {
+    int G = 1;
+    while (G * 64 < C) G <<= 1;
+    phase_sir_freq_l<64>(b, P, sm, G);
+  }
+}
+
+// ===================================================================== phase D
+// History flagger (Sec. 4.1): per channel, the mean of this block's unflagged
+// samples against mean + history_sensitivity * stddev of the committed means.
+template <bool INT>
+__device__ void phase_history(const DevBlock& b, const DevParams& P, Smem& sm) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int T = b.T, C = b.C;
+  const int W = (T + 63) >> 6;
+  const uint64_t* m0 = P.maskw + b.mask_off;
+  for (int i = tid; i < MAXC / 32; i += WG) sm.rowflag[i] = 0u;
+  if (b.stream_id < 0) {
+    __syncthreads();
+    return;
+  }
+  typedef typename PowT<INT>::T VT;
+  const int nch = (T + 7) >> 3;
+  for (int row = wv; row < C; row += NW) {
+    unsigned long long su = 0;
+    double sd = 0.0;
+    int cnt = 0;
+    for (int c = lane; c < nch; c += 64) {
+      const int t0 = c * 8;
+      const uint64_t w = ld_mask(m0 + (int64_t)row * W + (t0 >> 6));
+      const uint32_t fb = (uint32_t)(w >> (t0 & 63)) & 0xffu;
+      VT v[8];
+      const int nv = load8<INT>(b, row, t0, v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (j < nv && !((fb >> j) & 1u)) {
+          if (INT) su += (uint32_t)v[j];
+          else sd += (double)v[j];
+          ++cnt;
+        }
+      }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      su += __shfl_xor(su, d);
+      sd += __shfl_xor(sd, d);
+      cnt += __shfl_xor(cnt, d);
+    }
+    if (lane == 0) {
+      sm.u.c.rsum[row] = INT ? (double)su : sd;   // integer sums < 2^53: exact
+      sm.u.c.rcnt[row] = cnt;
+    }
+  }
+  __syncthreads();
+  const int s = b.stream_id;
+  for (int row = tid; row < C; row += WG) {
+    const int64_t idx = (int64_t)s * P.maxC + row;
+    const int cnt = sm.u.c.rcnt[row];
+    if (cnt == 0) {
+      P.pvalid[idx] = 0;
+      continue;
+    }
+    const double cur = sm.u.c.rsum[row] / (double)cnt;
+    const int L = P.rcount[idx];
+    bool flag = false;
+    double pushv = cur;
+    if (L >= P.Hmin) {
+      const int head = P.rhead[idx];
+      const double* ring = P.ring + idx * P.H;
+      double acc = 0.0;
+      for (int j = 0; j < L; ++j) {
+        int k = head - L + j;
+        if (k < 0) k += P.H;
+        acc += ring[k];
+      }
+      const double hm = acc / (double)L;
+      acc = 0.0;
+      for (int j = 0; j < L; ++j) {
+        int k = head - L + j;
+        if (k < 0) k += P.H;
+        const double d = ring[k] - hm;
+        acc += d * d;
+      }
+      const double hv = acc / (double)L;
+      const double thr = hm + P.hs * __builtin_sqrt(hv);
+      flag = P.literal ? (cur >= thr) : (cur > thr);
+      if (flag) pushv = thr;
+    }
+    P.pend[idx] = pushv;
+    P.pvalid[idx] = 1;
+    if (flag) atomicOr(&sm.rowflag[row >> 5], 1u << (row & 31));
+  }
+  __syncthreads();
+}
+
+// final flags = SIR mask OR history rows; one byte per sample
+__device__ void phase_write(const DevBlock& b, const DevParams& P, Smem& sm) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int T = b.T, C = b.C;
+  const int W = (T + 63) >> 6;
+  const uint64_t* m0 = P.maskw + b.mask_off;
+  const int nch = (T + 15) >> 4;
+  const int64_t items = (int64_t)C * nch;
+  unsigned long long nfl = 0;
+  for (int64_t it = tid; it < items; it += WG) {
+    const int row = (int)(it / nch);
+    const int t0 = (int)(it - (int64_t)row * nch) * 16;
+    const uint64_t w = ld_mask(m0 + (int64_t)row * W + (t0 >> 6));
+    uint32_t fb = (uint32_t)(w >> (t0 & 63)) & 0xffffu;
+    if ((sm.rowflag[row >> 5] >> (row & 31)) & 1u) fb = 0xffffu;
+    const int nv = min(16, T - t0);
+    fb &= (nv >= 16) ? 0xffffu : ((1u << nv) - 1u);
+    nfl += (unsigned long long)__builtin_popcount(fb);
+    uint8_t* fp = b.flags + (int64_t)row * b.fstride + t0;
+    if (b.faligned && nv == 16) {
+      uint32_t o[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t nib = (fb >> (4 * j)) & 0xfu;
+        o[j] = (nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21);
+      }
+      *(uint4*)fp = make_uint4(o[0], o[1], o[2], o[3]);
+    } else {
+      for (int j = 0; j < nv; ++j) fp[j] = (uint8_t)((fb >> j) & 1u);
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) nfl += __shfl_xor(nfl, d);
+  if (lane == 0) sm.red_u[0][wv] = nfl;
+  __syncthreads();
+  if (tid == 0 && P.stats) {
+    unsigned long long tot = 0;
+    for (int w = 0; w < NW; ++w) tot += sm.red_u[0][w];
+    int hr = 0;
+    for (int i = 0; i < MAXC / 32; ++i) hr += __builtin_popcount(sm.rowflag[i]);
+    double* st = (double*)((char*)P.stats + (int64_t)b.out_idx * (int64_t)(18 * 8 + 16));
+    st[0] = sm.median;
+    st[1] = sm.sigma;
+    const int nT = max(P.nl_t, P.nl_f);
+    for (int k = 0; k < 16; ++k) st[2 + k] = k < nT ? sm.T[k] : 0.0;
+    *(long long*)(st + 18) = (long long)tot;
+    *(int*)(st + 19) = hr;
+    *((int*)(st + 19) + 1) = 0;
+  }
+}
+
+// ===================================================================== kernels
+__device__ __forceinline__ void phase_sync() {
+  __threadfence();
+  __syncthreads();
+}
+
+template <bool INT, int L>
+__global__ __launch_bounds__(WG) void lof_flag_kernel(const DevBlock* __restrict__ blocks, DevParams P) {
+  __shared__ Smem sm;
+  const DevBlock b = blocks[blockIdx.x];
+  phase_stats<INT>(b, P, sm);
+  phase_time<INT, L>(b, P, sm);
+  phase_sync();
+  phase_freq<INT>(b, P, sm);
+  phase_sync();
+  if (P.eta_num > 0) {
+    phase_sir_time<L>(b, P, sm);
+    phase_sync();
+    phase_sir_freq(b, P, sm);
+    phase_sync();
+  }
+  phase_history<INT>(b, P, sm);
+  phase_write(b, P, sm);
+}
+
+// Commit staged history values (Sec. 4.1 addToHistory) of a list of streams.
+struct IdList {
+  int32_t n;
+  int32_t ids[255];
+};
+
+__global__ void lof_commit_kernel(IdList ids, int all_streams, DevParams P) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nsel = all_streams ? (int64_t)all_streams : (int64_t)ids.n;
+  if (i >= nsel * P.maxC) return;
+  const int si = (int)(i / P.maxC), c = (int)(i - (int64_t)si * P.maxC);
+  const int s = all_streams ? si : ids.ids[si];
+  const int64_t idx = (int64_t)s * P.maxC + c;
+  if (!P.pvalid[idx]) return;
+  const int h = P.rhead[idx];
+  P.ring[idx * P.H + h] = P.pend[idx];
+  P.rhead[idx] = (h + 1 == P.H) ? 0 : h + 1;
+  const int n = P.rcount[idx];
+  P.rcount[idx] = n < P.H ? n + 1 : P.H;
+  P.pvalid[idx] = 0;
+}
+
+// commit for the streams of a descriptor table (automatic commit)
+__global__ void lof_commit_desc_kernel(const DevBlock* __restrict__ blocks, int nb, DevParams P) {
+  const int bi = blockIdx.x;
+  if (bi >= nb) return;
+  const int s = blocks[bi].stream_id;
+  if (s < 0) return;
+  for (int c = threadIdx.x; c < P.maxC; c += blockDim.x) {
+    const int64_t idx = (int64_t)s * P.maxC + c;
+    if (!P.pvalid[idx]) continue;
+    const int h = P.rhead[idx];
+    P.ring[idx * P.H + h] = P.pend[idx];
+    P.rhead[idx] = (h + 1 == P.H) ? 0 : h + 1;
+    const int n = P.rcount[idx];
+    P.rcount[idx] = n < P.H ? n + 1 : P.H;
+    P.pvalid[idx] = 0;
+  }
+}
+
+}  // namespace lofk
