@@ -21,6 +21,19 @@
 
 namespace lofk {
 
+// Pointers held in descriptors are plain addresses; dereference them through the
+// global address space so the compiler emits global (not flat) memory
+// instructions, which do not share a wait counter with LDS traffic.
+#define GLB __attribute__((address_space(1)))
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+template <class T>
+__device__ __forceinline__ GLB T* gp(const void* p) {
+  return (GLB T*)(uintptr_t)p;
+}
+
+
 constexpr int WG = 512;            // threads per workgroup
 constexpr int NW = WG / 64;        // waves per workgroup
 constexpr int ST_MAX_LEVELS = 7;   // I <= 64: the dependency radius 120 and the packed
@@ -59,15 +72,16 @@ struct DevParams {
 };
 
 // ---------------------------------------------------------------- cross-lane
-// wave_shl:1 -> lane i reads lane i+1 (lane 63 reads 0); wave_shr:1 -> lane i reads i-1.
+// DPP moves with bound_ctrl: a lane whose source is outside the wave reads 0.
+// wave_shl:1 -> lane i reads lane i+1; wave_shr:1 -> lane i reads lane i-1.
 __device__ __forceinline__ uint32_t shl1(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, false);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xf, 0xf, true);
 }
 __device__ __forceinline__ float shl1(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 __device__ __forceinline__ uint32_t shr1(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, false);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138, 0xf, 0xf, true);
 }
 __device__ __forceinline__ uint64_t shr1_64(uint64_t v) {
   return (uint64_t)shr1((uint32_t)v) | ((uint64_t)shr1((uint32_t)(v >> 32)) << 32);
@@ -77,8 +91,8 @@ __device__ __forceinline__ uint64_t shl1_64(uint64_t v) {
 }
 // quad_perm [1,2,3,3]: lane j of a quad reads lane j+1 (lane 3 reads itself)
 __device__ __forceinline__ uint64_t quad_next_64(uint64_t v) {
-  uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, 0xF9, 0xf, 0xf, false);
-  uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), 0xF9, 0xf, 0xf, false);
+  uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, 0xF9, 0xf, 0xf, true);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), 0xF9, 0xf, 0xf, true);
   return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
@@ -87,14 +101,9 @@ __device__ __forceinline__ uint64_t lowmask(int n) {
 }
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
-// Loads of mask words written earlier in the kernel by other waves (possibly with
-// atomics, which complete in L2): read at agent scope so the vector L1 is bypassed.
-__device__ __forceinline__ uint64_t ld_mask(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void or_mask(uint64_t* p, uint64_t v) {
-  __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// Mask words are written with plain stores and read back by other waves of the
+// same workgroup after a barrier (same CU, so the same write-through L1).
+__device__ __forceinline__ uint64_t ld_mask(const GLB uint64_t* p) { return *p; }
 
 // ---------------------------------------------------------------- power (Sec. 4)
 // complex int8 sample packed in 16 bits (re low byte, im high byte): exact power.
@@ -109,16 +118,23 @@ __device__ __forceinline__ float c64_amp(float re, float im) { return __builtin_
 // power of one sample of a float-typed block (dtype 1, 2, 3)
 __device__ __forceinline__ float fpower_at(const DevBlock& b, int row, int t) {
   if (b.dtype == 2) {
-    return ((const float*)b.data)[(int64_t)row * b.dstride + t];
+    return gp<const float>(b.data)[(int64_t)row * b.dstride + t];
   }
-  const float2 z = ((const float2*)b.data)[(int64_t)row * b.dstride + t];
+  const f32x2 z = gp<const f32x2>(b.data)[(int64_t)row * b.dstride + t];
   return b.dtype == 1 ? c64_power(z.x, z.y) : c64_amp(z.x, z.y);
 }
 __device__ __forceinline__ uint32_t ipower_at(const DevBlock& b, int row, int t) {
-  return ci8_power(((const uint16_t*)b.data)[(int64_t)row * b.dstride + t]);
+  return ci8_power(gp<const uint16_t>(b.data)[(int64_t)row * b.dstride + t]);
 }
 
 // 8 consecutive samples of a row starting at t0 (vector loads when aligned and full)
+template <bool INT>
+struct TileOf;
+template <>
+struct TileOf<true> { typedef uint16_t T; };
+template <>
+struct TileOf<false> { typedef float T; };
+
 template <bool INT>
 struct PowT;
 template <>
@@ -130,9 +146,9 @@ template <bool INT>
 __device__ __forceinline__ int load8(const DevBlock& b, int row, int t0, typename PowT<INT>::T (&v)[8]) {
   const int nv = min(8, b.T - t0);
   if (INT) {
-    const uint8_t* rb = (const uint8_t*)b.data + (int64_t)row * b.dstride * 2;
+    const GLB uint8_t* rb = gp<const uint8_t>(b.data) + (int64_t)row * b.dstride * 2;
     if (b.aligned && nv == 8) {
-      const uint4 q = *(const uint4*)(rb + (int64_t)t0 * 2);
+      const u32x4 q = *(const GLB u32x4*)(rb + (int64_t)t0 * 2);
       const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -142,14 +158,14 @@ __device__ __forceinline__ int load8(const DevBlock& b, int row, int t0, typenam
     } else {
 #pragma unroll
       for (int j = 0; j < 8; ++j)
-        v[j] = (typename PowT<INT>::T)(j < nv ? ci8_power(*(const uint16_t*)(rb + (int64_t)(t0 + j) * 2)) : 0u);
+        v[j] = (typename PowT<INT>::T)(j < nv ? ci8_power(*(const GLB uint16_t*)(rb + (int64_t)(t0 + j) * 2)) : 0u);
     }
   } else {
     if (b.dtype == 2) {
-      const float* rb = (const float*)b.data + (int64_t)row * b.dstride;
+      const GLB float* rb = gp<const float>(b.data) + (int64_t)row * b.dstride;
       if (b.aligned && nv == 8) {
-        const float4 a = *(const float4*)(rb + t0);
-        const float4 c = *(const float4*)(rb + t0 + 4);
+        const f32x4 a = *(const GLB f32x4*)(rb + t0);
+        const f32x4 c = *(const GLB f32x4*)(rb + t0 + 4);
         v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
         v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
       } else {
@@ -157,12 +173,12 @@ __device__ __forceinline__ int load8(const DevBlock& b, int row, int t0, typenam
         for (int j = 0; j < 8; ++j) v[j] = j < nv ? rb[t0 + j] : 0.0f;
       }
     } else {
-      const float2* rb = (const float2*)b.data + (int64_t)row * b.dstride;
+      const GLB f32x2* rb = gp<const f32x2>(b.data) + (int64_t)row * b.dstride;
       const bool amp = b.dtype == 3;
       if (b.aligned && nv == 8) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const float4 a = *(const float4*)(rb + t0 + 2 * j);
+          const f32x4 a = *(const GLB f32x4*)(rb + t0 + 2 * j);
           v[2 * j] = amp ? c64_amp(a.x, a.y) : c64_power(a.x, a.y);
           v[2 * j + 1] = amp ? c64_amp(a.z, a.w) : c64_power(a.z, a.w);
         }
@@ -171,7 +187,7 @@ __device__ __forceinline__ int load8(const DevBlock& b, int row, int t0, typenam
         for (int j = 0; j < 8; ++j) {
           float r = 0.0f;
           if (j < nv) {
-            const float2 z = rb[t0 + j];
+            const f32x2 z = rb[t0 + j];
             r = amp ? c64_amp(z.x, z.y) : c64_power(z.x, z.y);
           }
           v[j] = r;
@@ -182,10 +198,55 @@ __device__ __forceinline__ int load8(const DevBlock& b, int row, int t0, typenam
   return nv;
 }
 
+// 8 samples with unconditional vector loads: rows 16-byte aligned and t0 + 8 <= T
+template <bool INT>
+__device__ __forceinline__ void load8v(const DevBlock& b, int row, int t0, typename PowT<INT>::T (&v)[8]) {
+  if (INT) {
+    const GLB uint8_t* rb = gp<const uint8_t>(b.data) + ((int64_t)row * b.dstride + t0) * 2;
+    const u32x4 q = *(const GLB u32x4*)rb;
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      v[2 * j] = (typename PowT<INT>::T)ci8_power(w[j] & 0xffffu);
+      v[2 * j + 1] = (typename PowT<INT>::T)ci8_power(w[j] >> 16);
+    }
+  } else if (b.dtype == 2) {
+    const GLB float* rb = gp<const float>(b.data) + (int64_t)row * b.dstride + t0;
+    const f32x4 a = *(const GLB f32x4*)rb;
+    const f32x4 c = *(const GLB f32x4*)(rb + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
+  } else {
+    const GLB f32x2* rb = gp<const f32x2>(b.data) + (int64_t)row * b.dstride + t0;
+    const bool amp = b.dtype == 3;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const f32x4 a = *(const GLB f32x4*)(rb + 2 * j);
+      v[2 * j] = amp ? c64_amp(a.x, a.y) : c64_power(a.x, a.y);
+      v[2 * j + 1] = amp ? c64_amp(a.z, a.w) : c64_power(a.z, a.w);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- shared memory
-struct Smem {
+constexpr int IHIST_WORDS = 16385;   // 32769 integer-power bins, two 16-bit counters per word
+constexpr int TILE_ELEMS = NW * 64 * 32;   // frequency slab: (G*32 channels) x (NW*64/G columns)
+constexpr int TILE_PAD = 1024;             // one padding element per slab row (<= 1024 rows)
+constexpr int TILE_WORDS = 1024;           // mask words of one frequency slab
+
+template <bool INT>
+struct SmemT {
+  typedef typename TileOf<INT>::T TileT;
+  // integer slabs hold 64 columns per wave (one lane per column, up to 64
+  // channels): 64 x 513 u16; float slabs the generic (G*32) x (NW*64/G + 1)
+  static constexpr int TE = INT ? (64 * (NW * 64 + 1)) : (TILE_ELEMS + TILE_PAD);
   union {
-    uint32_t hist[2][HBINS];                 // phase A
+    uint32_t ihist[INT ? IHIST_WORDS : 1];   // phase A, integer input: full-resolution histogram
+    uint32_t hist[2][HBINS];                 // phase A: 12-bit digit histograms (radix select)
+    struct {
+      TileT t[TE];                           // frequency slab of powers (u16 values / float)
+      uint64_t w[TILE_WORDS];                // mask words of the slab
+    } f;
     struct {
       double rsum[MAXC];                     // history: per-row unflagged sum
       int32_t rcnt[MAXC];                    // history: per-row unflagged count

@@ -6,15 +6,36 @@
 
 namespace lofk {
 
+// Exact unsigned 32-bit division by a block-uniform divisor d >= 1 (round-up
+// multiplier method: l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1,
+// q = (hi + ((n - hi) >> 1)) >> (l - 1) with hi = mulhi(m, n); l = 0 for d = 1).
+struct FastDiv {
+  uint32_t d, m;
+  int l;
+  __device__ explicit FastDiv(uint32_t dd) : d(dd) {
+    l = 0;
+    while ((1ull << l) < dd) ++l;
+    m = (uint32_t)((((1ull << l) - dd) << 32) / dd + 1ull);
+  }
+  __device__ __forceinline__ uint32_t div(uint32_t n) const {
+    if (l == 0) return n;
+    const uint32_t hi = __umulhi(m, n);
+    return (hi + ((n - hi) >> 1)) >> (l - 1);
+  }
+};
+
 // ===================================================================== phase A
 // Block median and population standard deviation over all C*T samples
-// (Sec. 2.1 threshold definition; Sec. 4.2 asks for an O(N) median): one pass
-// accumulates exact (integer input) or float64 moments and the top 12-bit digit
-// histogram of an order-preserving 32-bit key; further passes refine the digit
-// of the two middle order statistics.  Then the thresholds of Sec. 2.1.
+// (Sec. 2.1 threshold definition; Sec. 4.2 asks for an O(N) median).
+// Integer input: one pass accumulates exact moments and a full-resolution
+// histogram of the integer power (32769 bins as 16-bit counters, two per LDS
+// word); if any bin could have wrapped (the 16-bit fields no longer sum to N) the
+// block falls back to a 2-pass radix select.  Float input: 3-pass radix select
+// over an order-preserving 32-bit key (12 + 12 + 8 bits), float64 moments.
 
-// block-wide: bin holding `rank` (0-based) in the 4096-bin histogram h
-__device__ void find_bin(const uint32_t* h, uint32_t rank, Smem& sm, uint32_t& bin, uint32_t& rem) {
+// block-wide: bin holding `rank` (0-based) of a 4096-bin histogram
+template <class SM>
+__device__ void find_bin(const uint32_t* h, uint32_t rank, SM& sm, uint32_t& bin, uint32_t& rem) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   constexpr int PER = HBINS / WG;
   uint32_t loc[PER];
@@ -53,6 +74,53 @@ __device__ void find_bin(const uint32_t* h, uint32_t rank, Smem& sm, uint32_t& b
   __syncthreads();
 }
 
+// block-wide: value (bin) holding `rank` in the packed 32769-bin histogram;
+// thread t owns words [32t, 32t+32), the last thread also word 16384.
+template <class SM>
+__device__ uint32_t find_bin16(const uint32_t* h, uint32_t rank, SM& sm) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int PW = (IHIST_WORDS - 1) / WG;   // 32
+  const int w0 = tid * PW;
+  const int nw = PW + (tid == WG - 1 ? 1 : 0);
+  uint32_t s = 0;
+  for (int j = 0; j < nw; ++j) {
+    const uint32_t w = h[w0 + j];
+    s += (w & 0xffffu) + (w >> 16);
+  }
+  uint32_t x = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) sm.scan[wv] = x;
+  __syncthreads();
+  uint32_t off = 0;
+  for (int w = 0; w < wv; ++w) off += sm.scan[w];
+  const uint32_t excl = off + x - s;
+  if (rank >= excl && rank < excl + s) {
+    uint32_t c = excl;
+    for (int j = 0; j < nw; ++j) {
+      const uint32_t w = h[w0 + j];
+      const uint32_t lo = w & 0xffffu, hi = w >> 16;
+      if (rank < c + lo) {
+        sm.sel[0] = (uint32_t)(2 * (w0 + j));
+        break;
+      }
+      c += lo;
+      if (rank < c + hi) {
+        sm.sel[0] = (uint32_t)(2 * (w0 + j) + 1);
+        break;
+      }
+      c += hi;
+    }
+  }
+  __syncthreads();
+  const uint32_t v = sm.sel[0];
+  __syncthreads();
+  return v;
+}
+
 __device__ __forceinline__ uint32_t fkey(float v) {
   const uint32_t u = __float_as_uint(v);
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
@@ -61,87 +129,40 @@ __device__ __forceinline__ float fkey_inv(uint32_t k) {
   return __uint_as_float((k & 0x80000000u) ? (k ^ 0x80000000u) : ~k);
 }
 
-template <bool INT>
-__device__ void phase_stats(const DevBlock& b, const DevParams& P, Smem& sm) {
+// Radix select of the order statistics r0 <= r1 over the block's keys.
+// Integer keys: 16 bits as 12 + 4; float keys: 32 bits as 12 + 12 + 8.
+// If have_pass0, hist[0] already holds the first-digit histogram.
+template <bool INT, class SM>
+__device__ __forceinline__ void radix_select(const DevBlock& b, SM& sm, uint32_t r0, uint32_t r1, bool have_pass0,
+                             uint32_t& k0, uint32_t& k1) {
   typedef typename PowT<INT>::T VT;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x;
   const int nch = (b.T + 7) >> 3;
-  const int64_t items = (int64_t)b.C * nch;
-  const int64_t N = (int64_t)b.C * b.T;
-  const int KB = INT ? 16 : 32;  // key bits (integer power <= 32768 < 2^16)
+  const uint32_t items = (uint32_t)b.C * (uint32_t)nch;
+  const FastDiv fd((uint32_t)nch);
+  const int KB = INT ? 16 : 32;
   const int npass = INT ? 2 : 3;
   const int dbits[3] = {12, INT ? 4 : 12, 8};
-
-  for (int i = tid; i < 2 * HBINS; i += WG) (&sm.u.hist[0][0])[i] = 0u;
-  __syncthreads();
-
-  unsigned long long s1u = 0, s2u = 0;
-  double s1d = 0.0, s2d = 0.0;
-  {
-    const int lo = KB - 12;
-    for (int64_t it = tid; it < items; it += WG) {
-      const int row = (int)(it / nch);
-      const int t0 = (int)(it - (int64_t)row * nch) * 8;
-      VT v[8];
-      const int nv = load8<INT>(b, row, t0, v);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        if (j < nv) {
-          uint32_t key;
-          if (INT) {
-            const uint32_t p = (uint32_t)v[j];
-            s1u += p;
-            s2u += (unsigned long long)p * p;
-            key = p;
-          } else {
-            const double d = (double)v[j];
-            s1d += d;
-            s2d += d * d;
-            key = fkey((float)v[j]);
-          }
-          atomicAdd(&sm.u.hist[0][key >> lo], 1u);
-        }
-      }
-    }
-  }
-  // block reduction of the moments (fixed order: deterministic)
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    s1u += __shfl_xor(s1u, d);
-    s2u += __shfl_xor(s2u, d);
-    s1d += __shfl_xor(s1d, d);
-    s2d += __shfl_xor(s2d, d);
-  }
-  if (lane == 0) {
-    sm.red_u[0][wv] = s1u;
-    sm.red_u[1][wv] = s2u;
-    sm.red_d[0][wv] = s1d;
-    sm.red_d[1][wv] = s2d;
-  }
-  __syncthreads();
-
-  // radix select of ranks (N-1)/2 and N/2
-  uint32_t r0 = (uint32_t)((N - 1) / 2), r1 = (uint32_t)(N / 2);
   uint32_t pre0 = 0, pre1 = 0;
   int hi = KB;
   for (int pass = 0; pass < npass; ++pass) {
     const int db = dbits[pass];
     const int lo = hi - db;
     const uint32_t dmask = (1u << db) - 1u;
-    if (pass > 0) {
+    if (pass > 0 || !have_pass0) {
       for (int i = tid; i < 2 * HBINS; i += WG) (&sm.u.hist[0][0])[i] = 0u;
       __syncthreads();
       const bool two = pre1 != pre0;
-      for (int64_t it = tid; it < items; it += WG) {
-        const int row = (int)(it / nch);
-        const int t0 = (int)(it - (int64_t)row * nch) * 8;
+      for (uint32_t it = tid; it < items; it += WG) {
+        const int row = (int)fd.div(it);
+        const int t0 = (int)(it - (uint32_t)row * (uint32_t)nch) * 8;
         VT v[8];
         const int nv = load8<INT>(b, row, t0, v);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           if (j < nv) {
             const uint32_t key = INT ? (uint32_t)v[j] : fkey((float)v[j]);
-            const uint32_t top = key >> hi;
+            const uint32_t top = pass == 0 ? 0u : (key >> hi);
             const uint32_t dg = (key >> lo) & dmask;
             if (top == pre0) atomicAdd(&sm.u.hist[0][dg], 1u);
             if (two && top == pre1) atomicAdd(&sm.u.hist[1][dg], 1u);
@@ -160,6 +181,112 @@ __device__ void phase_stats(const DevBlock& b, const DevParams& P, Smem& sm) {
     r1 = q1;
     hi = lo;
   }
+  k0 = pre0;
+  k1 = pre1;
+}
+
+template <bool INT, class SM>
+__device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& P, SM& sm) {
+  typedef typename PowT<INT>::T VT;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nch = (b.T + 7) >> 3;
+  const uint32_t items = (uint32_t)b.C * (uint32_t)nch;
+  const FastDiv fd((uint32_t)nch);
+  const int64_t N = (int64_t)b.C * b.T;
+
+  if (INT) {
+    for (int i = tid; i < IHIST_WORDS; i += WG) sm.u.ihist[i] = 0u;
+  } else {
+    for (int i = tid; i < 2 * HBINS; i += WG) (&sm.u.hist[0][0])[i] = 0u;
+  }
+  __syncthreads();
+
+  unsigned long long s1u = 0, s2u = 0;
+  double s1d = 0.0, s2d = 0.0;
+  constexpr int U = 4;   // chunks of 8 samples in flight per thread
+  auto consume = [&](const VT (&v)[8], int nv) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j < nv) {
+        if (INT) {
+          const uint32_t p = (uint32_t)v[j];
+          s1u += p;
+          s2u += (unsigned long long)(p * p);     // p <= 32768: p*p < 2^31
+          atomicAdd(&sm.u.ihist[p >> 1], (p & 1u) ? 0x10000u : 1u);
+        } else {
+          const double d = (double)v[j];
+          s1d += d;
+          s2d += d * d;
+          atomicAdd(&sm.u.hist[0][fkey((float)v[j]) >> 20], 1u);
+        }
+      }
+    }
+  };
+  if (b.aligned && (b.T & 7) == 0) {
+    // every chunk full and aligned: unconditional loads (clamped index, masked
+    // count) so all U loads of a thread are in flight together
+    for (uint32_t base = tid; base < items; base += (uint32_t)WG * U) {
+      VT v[U][8];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t it = base + (uint32_t)u * WG;
+        const uint32_t ic = it < items ? it : items - 1;
+        const int row = (int)fd.div(ic);
+        const int t0 = (int)(ic - (uint32_t)row * (uint32_t)nch) * 8;
+        load8v<INT>(b, row, t0, v[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) consume(v[u], base + (uint32_t)u * WG < items ? 8 : 0);
+    }
+  } else {
+    for (uint32_t it = tid; it < items; it += WG) {
+      const int row = (int)fd.div(it);
+      const int t0 = (int)(it - (uint32_t)row * (uint32_t)nch) * 8;
+      VT v[8];
+      const int nv = load8<INT>(b, row, t0, v);
+      consume(v, nv);
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    s1u += __shfl_xor(s1u, d);
+    s2u += __shfl_xor(s2u, d);
+    s1d += __shfl_xor(s1d, d);
+    s2d += __shfl_xor(s2d, d);
+  }
+  if (lane == 0) {
+    sm.red_u[0][wv] = s1u;
+    sm.red_u[1][wv] = s2u;
+    sm.red_d[0][wv] = s1d;
+    sm.red_d[1][wv] = s2d;
+  }
+  __syncthreads();
+
+  const uint32_t r0 = (uint32_t)((N - 1) / 2), r1 = (uint32_t)(N / 2);
+  uint32_t k0, k1;
+  if (INT) {
+    // the 16-bit fields sum to N exactly when no counter wrapped
+    uint32_t s = 0;
+    for (int i = tid; i < IHIST_WORDS; i += WG) {
+      const uint32_t w = sm.u.ihist[i];
+      s += (w & 0xffffu) + (w >> 16);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+    if (lane == 0) sm.scan[wv] = s;
+    __syncthreads();
+    uint32_t tot = 0;
+    for (int w = 0; w < NW; ++w) tot += sm.scan[w];
+    __syncthreads();
+    if (tot == (uint32_t)N) {
+      k0 = find_bin16(sm.u.ihist, r0, sm);
+      k1 = (r1 == r0) ? k0 : find_bin16(sm.u.ihist, r1, sm);
+    } else {
+      radix_select<INT>(b, sm, r0, r1, false, k0, k1);
+    }
+  } else {
+    radix_select<INT>(b, sm, r0, r1, true, k0, k1);
+  }
 
   if (tid == 0) {
     unsigned long long S1u = 0, S2u = 0;
@@ -172,11 +299,11 @@ __device__ void phase_stats(const DevBlock& b, const DevParams& P, Smem& sm) {
     }
     double v0, v1;
     if (INT) {
-      v0 = (double)pre0;
-      v1 = (double)pre1;
+      v0 = (double)k0;
+      v1 = (double)k1;
     } else {
-      v0 = (double)fkey_inv(pre0);
-      v1 = (double)fkey_inv(pre1);
+      v0 = (double)fkey_inv(k0);
+      v1 = (double)fkey_inv(k1);
     }
     const double med = (N & 1) ? v0 : (v0 + v1) / 2.0;
     const double n = (double)N;
@@ -239,7 +366,8 @@ __device__ void phase_stats(const DevBlock& b, const DevParams& P, Smem& sm) {
 // Integer input: v = p*512 + 4 for an unflagged sample, 0 for a flagged one, so a
 // window word D = S*512 + 4c packs the exact unflagged sum S and count c; the test
 // S > floor(c*T_k) is D > G_k[c].  Float input: float32 sums and counts, test
-// S > c*T_k in float32.
+// S > c*T_k in float32.  Window sums of level k are D_k(s) = D_{k-1}(s) +
+// D_{k-1}(s + I/2); after a level that changed the mask they are rebuilt from v.
 
 template <int L, int H, class VT>
 __device__ __forceinline__ void dbl_step(VT (&D)[L]) {
@@ -254,23 +382,18 @@ __device__ __forceinline__ void dbl_step(VT (&D)[L]) {
   }
 }
 
-template <int L, class VT>
-__device__ __forceinline__ void dbl_h(VT (&D)[L], int h) {
-  switch (h) {
-    case 1: dbl_step<L, 1>(D); break;
-    case 2: dbl_step<L, 2>(D); break;
-    case 4: dbl_step<L, 4>(D); break;
-    case 8: dbl_step<L, 8>(D); break;
-    case 16: if constexpr (L >= 16) dbl_step<L, 16>(D); break;
-    case 32: if constexpr (L >= 32) dbl_step<L, 32>(D); break;
-    default: break;
+template <int L, int J, int M, class VT>
+__device__ __forceinline__ void rebuild(VT (&D)[L]) {
+  if constexpr (J < M) {
+    dbl_step<L, (1 << J)>(D);
+    rebuild<L, J + 1, M>(D);
   }
 }
 
 // window-start bits wf (bit i <-> start lig*L+i) -> flagged positions of this lane:
 // OR over starts s in [j-I+1, j], with starts of up to two lanes to the left.
-template <int L>
-__device__ __forceinline__ uint64_t spread(uint64_t wf, int lig, int I) {
+template <int L, int I>
+__device__ __forceinline__ uint64_t spread(uint64_t wf, int lig) {
   uint64_t p1 = shr1_64(wf);
   uint64_t p2 = 0;
   if (L < 64) p2 = shr1_64(p1);
@@ -282,6 +405,7 @@ __device__ __forceinline__ uint64_t spread(uint64_t wf, int lig, int I) {
   else if (L == 32) xlo = (p1 << 32) | p2;
   else xlo = 0;  // L < 32 only with groups of one lane
   uint64_t xhi = wf;
+#pragma unroll
   for (int d = 1; d < I; d <<= 1) {
     xhi |= (xhi << d) | (xlo >> (64 - d));
     xlo |= xlo << d;
@@ -289,115 +413,160 @@ __device__ __forceinline__ uint64_t spread(uint64_t wf, int lig, int I) {
   return xhi;
 }
 
-// Loader interface: fill(fm, D, N) sets D (and N, float path) to the level-0
+template <bool INT, int L, int K, class LD, class SM>
+__device__ __forceinline__ void st_level(LD& ld, typename PowT<INT>::T (&D)[L], float (&Nc)[L], uint64_t& fm,
+                                         bool& dirty, const int lig, const int n, const int pos0,
+                                         const uint64_t vmask, const SM& sm) {
+  constexpr int I = 1 << K;
+  if constexpr ((I >> 1) <= L) {
+    if constexpr (K > 0) {
+      if (dirty) {
+        ld.fill(fm, D, Nc);
+        rebuild<L, 0, K - 1>(D);
+        if constexpr (!INT) rebuild<L, 0, K - 1>(Nc);
+      }
+      dbl_step<L, (I >> 1)>(D);
+      if constexpr (!INT) dbl_step<L, (I >> 1)>(Nc);
+    }
+    // judge the windows: first only whether any window of the wave exceeds
+    // (compare + scalar OR; windows past the sequence end may raise a false
+    // alarm, which costs only the second loop), then the per-lane window bits.
+    const int nvw = n - I + 1 - pos0;      // valid window starts in this lane: i < nvw
+    unsigned long long any = 0;
+    uint32_t lo = 0, hi = 0;
+    if constexpr (INT) {
+      const int32_t* Gk = sm.G[K];
+      bool scalar = false;
+      if constexpr (K == 0) scalar = __ballot(fm != 0) == 0;
+      if (scalar) {
+        const int32_t g = Gk[1];
+#pragma unroll
+        for (int i = 0; i < L; ++i) any |= __ballot((int32_t)(uint32_t)D[i] > g);
+        if (any) {
+#pragma unroll
+          for (int i = 0; i < L; ++i) {
+            const uint32_t h = ((int32_t)(uint32_t)D[i] > g) ? 1u : 0u;
+            if (i < 32) lo |= h << i; else hi |= h << (i - 32);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+          const uint32_t d = (uint32_t)D[i];
+          any |= __ballot((int32_t)d > Gk[(d >> 2) & 127u]);
+          if ((i & 15) == 15) __builtin_amdgcn_sched_barrier(0);   // bound the hoisted table reads
+        }
+        if (any) {
+#pragma unroll
+          for (int i = 0; i < L; ++i) {
+            const uint32_t d = (uint32_t)D[i];
+            const uint32_t h = ((int32_t)d > Gk[(d >> 2) & 127u]) ? 1u : 0u;
+            if (i < 32) lo |= h << i; else hi |= h << (i - 32);
+            if ((i & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+      }
+    } else {
+      const float Tk = sm.Tf[K];
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        const float c = Nc[i];
+        any |= __ballot(c > 0.0f && (float)D[i] > c * Tk);
+      }
+      if (any) {
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+          const float c = Nc[i];
+          const uint32_t h = (c > 0.0f && (float)D[i] > c * Tk) ? 1u : 0u;
+          if (i < 32) lo |= h << i; else hi |= h << (i - 32);
+        }
+      }
+    }
+    if (any == 0) {
+      dirty = false;
+      return;
+    }
+    uint64_t wf = (uint64_t)lo | ((uint64_t)hi << 32);
+    wf &= lowmask(nvw) & vmask;
+    const uint64_t nb = spread<L, I>(wf, lig) & vmask;
+    const uint64_t changed = nb & ~fm;
+    fm |= nb;
+    dirty = __ballot(changed != 0) != 0;
+  }
+}
+
+// Loader interface: fill(fm, D, Nc) sets D (and Nc, float path) to the level-0
 // window values of the lane's L positions under mask fm.
-template <bool INT, int L, class LD>
-__device__ uint64_t st_core(LD& ld, uint64_t fm, const int lig, const int n, const int kfirst,
-                            const int nlev, const Smem& sm) {
+template <bool INT, int L, class LD, class SM>
+__device__ __forceinline__ uint64_t st_core(LD& ld, uint64_t fm, const int lig, const int n, const int kfirst,
+                            const int nlev, const SM& sm) {
   typedef typename PowT<INT>::T VT;
   VT D[L];
   float Nc[L];
   const int pos0 = lig * L;
   const int nval = clampi(n - pos0, 0, L);
   const uint64_t vmask = lowmask(nval);
+  int kend = 0;
+  while (kend < nlev && (1 << kend) <= n) ++kend;   // levels with I <= n
   ld.fill(fm, D, Nc);
   bool dirty = false;
-  for (int k = kfirst; k < nlev; ++k) {
-    const int I = 1 << k;
-    if (I > n) break;
-    if (k > 0) {
-      if (dirty) {
-        ld.fill(fm, D, Nc);
-        for (int j = 0; j + 1 < k; ++j) {
-          dbl_h<L>(D, 1 << j);
-          if constexpr (!INT) dbl_h<L>(Nc, 1 << j);
-        }
-      }
-      dbl_h<L>(D, I >> 1);
-      if constexpr (!INT) dbl_h<L>(Nc, I >> 1);
-    }
-    // judge the windows of this level
-    uint32_t lo = 0, hi = 0;
-    if (INT) {
-      const int32_t* Gk = sm.G[k];
-      const bool clean = __ballot(fm != 0) == 0;
-      if (k == 0 && clean) {
-        const int32_t g = Gk[1];
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-          const uint32_t h = ((int32_t)(uint32_t)D[i] > g) ? 1u : 0u;
-          if (i < 32) lo |= h << i; else hi |= h << (i - 32);
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-          const uint32_t d = (uint32_t)D[i];
-          const uint32_t h = ((int32_t)d > Gk[(d >> 2) & 127u]) ? 1u : 0u;
-          if (i < 32) lo |= h << i; else hi |= h << (i - 32);
-        }
-      }
-    } else {
-      const float Tk = sm.Tf[k];
-#pragma unroll
-      for (int i = 0; i < L; ++i) {
-        const float c = Nc[i];
-        const uint32_t h = (c > 0.0f && (float)D[i] > c * Tk) ? 1u : 0u;
-        if (i < 32) lo |= h << i; else hi |= h << (i - 32);
-      }
-    }
-    uint64_t wf = (uint64_t)lo | ((uint64_t)hi << 32);
-    wf &= lowmask(n - I + 1 - pos0) & vmask;
-    if (__ballot(wf != 0) == 0) {
-      dirty = false;
-      continue;
-    }
-    const uint64_t nb = spread<L>(wf, lig, I) & vmask;
-    const uint64_t changed = nb & ~fm;
-    fm |= nb;
-    dirty = __ballot(changed != 0) != 0;
-  }
+#define LOF_LEVEL(K) \
+  if (kfirst <= K && K < kend) st_level<INT, L, K>(ld, D, Nc, fm, dirty, lig, n, pos0, vmask, sm);
+  LOF_LEVEL(0)
+  LOF_LEVEL(1)
+  LOF_LEVEL(2)
+  LOF_LEVEL(3)
+  LOF_LEVEL(4)
+  LOF_LEVEL(5)
+  LOF_LEVEL(6)
+#undef LOF_LEVEL
   return fm;
 }
 
 // ---- loaders
+struct RowSrc {        // the descriptor fields a row loader needs, by value
+  const void* data;
+  int64_t dstride;
+  int dtype, aligned;
+  __device__ explicit RowSrc(const DevBlock& d) : data(d.data), dstride(d.dstride), dtype(d.dtype), aligned(d.aligned) {}
+};
+
 template <bool INT, int L>
 struct TimeLoader {
-  const DevBlock* b;
+  RowSrc s;
   int row, q, nval;   // q: absolute time of the lane's first position
   bool ok;
   __device__ __forceinline__ void fill(uint64_t fm, typename PowT<INT>::T (&D)[L], float (&Nc)[L]) {
     if (INT) {
-      const uint8_t* rb = (const uint8_t*)b->data + ((int64_t)row * b->dstride + q) * 2;
-      uint32_t p[L];
-      if (ok && nval == L && b->aligned) {
+      const GLB uint8_t* rb = gp<const uint8_t>(s.data) + ((int64_t)row * s.dstride + q) * 2;
+      if (ok && nval == L && s.aligned) {
 #pragma unroll
         for (int j = 0; j < L / 8; ++j) {
-          const uint4 w = *(const uint4*)(rb + 16 * j);
+          const u32x4 w = *(const GLB u32x4*)(rb + 16 * j);
           const uint32_t a[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
-            p[8 * j + 2 * m] = ci8_power(a[m] & 0xffffu);
-            p[8 * j + 2 * m + 1] = ci8_power(a[m] >> 16);
+            const int i0 = 8 * j + 2 * m;
+            const uint32_t p0 = ci8_power(a[m] & 0xffffu), p1 = ci8_power(a[m] >> 16);
+            D[i0] = ((fm >> i0) & 1ull) ? 0u : p0 * 512u + 4u;
+            D[i0 + 1] = ((fm >> (i0 + 1)) & 1ull) ? 0u : p1 * 512u + 4u;
           }
         }
       } else {
 #pragma unroll
-        for (int i = 0; i < L; ++i)
-          p[i] = (ok && i < nval) ? ci8_power(*(const uint16_t*)(rb + 2 * i)) : 0u;
-      }
-#pragma unroll
-      for (int i = 0; i < L; ++i) {
-        const bool live = i < nval && ok && !((fm >> i) & 1ull);
-        D[i] = (typename PowT<INT>::T)(live ? p[i] * 512u + 4u : 0u);
+        for (int i = 0; i < L; ++i) {
+          const bool live = ok && i < nval && !((fm >> i) & 1ull);
+          D[i] = live ? ci8_power(*(const GLB uint16_t*)(rb + 2 * i)) * 512u + 4u : 0u;
+        }
       }
     } else {
       float p[L];
-      if (b->dtype == 2) {
-        const float* rb = (const float*)b->data + (int64_t)row * b->dstride + q;
-        if (ok && nval == L && b->aligned) {
+      if (s.dtype == 2) {
+        const GLB float* rb = gp<const float>(s.data) + (int64_t)row * s.dstride + q;
+        if (ok && nval == L && s.aligned) {
 #pragma unroll
           for (int j = 0; j < L / 4; ++j) {
-            const float4 w = *(const float4*)(rb + 4 * j);
+            const f32x4 w = *(const GLB f32x4*)(rb + 4 * j);
             p[4 * j] = w.x; p[4 * j + 1] = w.y; p[4 * j + 2] = w.z; p[4 * j + 3] = w.w;
           }
         } else {
@@ -405,12 +574,12 @@ struct TimeLoader {
           for (int i = 0; i < L; ++i) p[i] = (ok && i < nval) ? rb[i] : 0.0f;
         }
       } else {
-        const float2* rb = (const float2*)b->data + (int64_t)row * b->dstride + q;
-        const bool amp = b->dtype == 3;
-        if (ok && nval == L && b->aligned) {
+        const GLB f32x2* rb = gp<const f32x2>(s.data) + (int64_t)row * s.dstride + q;
+        const bool amp = s.dtype == 3;
+        if (ok && nval == L && s.aligned) {
 #pragma unroll
           for (int j = 0; j < L / 2; ++j) {
-            const float4 w = *(const float4*)(rb + 2 * j);
+            const f32x4 w = *(const GLB f32x4*)(rb + 2 * j);
             p[2 * j] = amp ? c64_amp(w.x, w.y) : c64_power(w.x, w.y);
             p[2 * j + 1] = amp ? c64_amp(w.z, w.w) : c64_power(w.z, w.w);
           }
@@ -419,7 +588,7 @@ struct TimeLoader {
           for (int i = 0; i < L; ++i) {
             float r = 0.0f;
             if (ok && i < nval) {
-              const float2 z = rb[i];
+              const f32x2 z = rb[i];
               r = amp ? c64_amp(z.x, z.y) : c64_power(z.x, z.y);
             }
             p[i] = r;
@@ -436,21 +605,22 @@ struct TimeLoader {
   }
 };
 
+// frequency loader: one column of the LDS slab (rows = channels)
 template <bool INT, int L>
-struct FreqLoader {
-  const DevBlock* b;
-  int t, ch0, nval;   // column, first channel of the lane, valid channels in lane
-  bool ok;            // t < T
+struct TileLoader {
+  const typename TileOf<INT>::T* tile;
+  int stride, col, ch0, nval;
+  bool ok;
   __device__ __forceinline__ void fill(uint64_t fm, typename PowT<INT>::T (&D)[L], float (&Nc)[L]) {
 #pragma unroll
     for (int i = 0; i < L; ++i) {
       const bool valid = ok && i < nval;
       const bool live = valid && !((fm >> i) & 1ull);
       if (INT) {
-        const uint32_t p = valid ? ipower_at(*b, ch0 + i, t) : 0u;
+        const uint32_t p = valid ? (uint32_t)tile[(ch0 + i) * stride + col] : 0u;
         D[i] = (typename PowT<INT>::T)(live ? p * 512u + 4u : 0u);
       } else {
-        const float p = valid ? fpower_at(*b, ch0 + i, t) : 0.0f;
+        const float p = valid ? (float)tile[(ch0 + i) * stride + col] : 0.0f;
         D[i] = (typename PowT<INT>::T)(live ? p : 0.0f);
         Nc[i] = live ? 1.0f : 0.0f;
       }
@@ -460,7 +630,7 @@ struct FreqLoader {
 
 // ---- bit output of a row layout (lane bits at lig*L) into u64 row words
 template <int L>
-__device__ __forceinline__ void write_row_bits(uint64_t* rowp, int W, uint64_t fm, int lig, int G, bool ok) {
+__device__ __forceinline__ void write_row_bits(GLB uint64_t* rowp, int W, uint64_t fm, int lig, int G, bool ok) {
   if (L == 64) {
     if (ok && lig < W) rowp[lig] = fm;
   } else if (L == 32) {
@@ -483,20 +653,26 @@ __device__ __forceinline__ void write_row_bits(uint64_t* rowp, int W, uint64_t f
   }
 }
 
-__device__ __forceinline__ uint64_t get_bits(const uint64_t* rowp, int W, int q, int L) {
+__device__ __forceinline__ uint64_t get_bits(const GLB uint64_t* rowp, int W, int q, int L) {
   const int w = q >> 6, o = q & 63;
   uint64_t r = (w < W) ? (ld_mask(rowp + w) >> o) : 0ull;
   if (o != 0 && o + L > 64 && w + 1 < W) r |= ld_mask(rowp + w + 1) << (64 - o);
   return r & lowmask(L);
 }
 
+// set one bit of a u64 word array in LDS (32-bit atomic on the half that holds it)
+__device__ __forceinline__ void or_bit_lds(uint64_t* w, int idx, int bit) {
+  uint32_t* h = reinterpret_cast<uint32_t*>(w) + 2 * idx + (bit >> 5);
+  atomicOr(h, 1u << (bit & 31));
+}
+
 // ===================================================================== phase B
-template <bool INT, int L>
-__device__ void phase_time(const DevBlock& b, const DevParams& P, Smem& sm) {
+template <bool INT, int L, class SM>
+__device__ __forceinline__ void phase_time(const DevBlock& b, const DevParams& P, SM& sm) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int T = b.T, C = b.C;
   const int W = (T + 63) >> 6;
-  uint64_t* m0 = P.maskw + b.mask_off;
+  GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
   const int nlev = min(P.nl_t, ST_MAX_LEVELS);
   if (T <= 64 * L) {
     int G = 1;
@@ -505,7 +681,7 @@ __device__ void phase_time(const DevBlock& b, const DevParams& P, Smem& sm) {
     for (int rb = wv * R; rb < C; rb += NW * R) {
       const int row = rb + grp;
       const bool ok = row < C;
-      TimeLoader<INT, L> ld{&b, ok ? row : 0, lig * L, clampi(T - lig * L, 0, L), ok};
+      TimeLoader<INT, L> ld{RowSrc(b), ok ? row : 0, lig * L, clampi(T - lig * L, 0, L), ok};
       const uint64_t fm = st_core<INT, L>(ld, 0ull, lig, T, 0, nlev, sm);
       write_row_bits<L>(m0 + (int64_t)(ok ? row : 0) * W, W, fm, lig, G, ok);
     }
@@ -516,7 +692,7 @@ __device__ void phase_time(const DevBlock& b, const DevParams& P, Smem& sm) {
         const int c1 = min(T, c0 + SEG_CORE);
         const int q0 = max(0, c0 - SEG_HALO);
         const int n = min(T, q0 + 64 * L) - q0;
-        TimeLoader<INT, L> ld{&b, row, q0 + lane * L, clampi(n - lane * L, 0, L), true};
+        TimeLoader<INT, L> ld{RowSrc(b), row, q0 + lane * L, clampi(n - lane * L, 0, L), true};
         const uint64_t fm = st_core<INT, L>(ld, 0ull, lane, n, 0, nlev, sm);
         const int pos = q0 + lane * L;   // L == 64: one word per lane
         if (L == 64 && pos >= c0 && pos < c1) m0[(int64_t)row * W + (pos >> 6)] = fm;
@@ -525,64 +701,226 @@ __device__ void phase_time(const DevBlock& b, const DevParams& P, Smem& sm) {
   }
 }
 
-// frequency SumThreshold (Sec. 2.1, the other direction), starting from the time mask
-template <bool INT, int LF>
-__device__ void phase_freq_l(const DevBlock& b, const DevParams& P, Smem& sm, int G) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int T = b.T, C = b.C;
-  const int W = (T + 63) >> 6;
-  uint64_t* m0 = P.maskw + b.mask_off;
-  const int nlev = min(P.nl_f, ST_MAX_LEVELS);
-  const int CPW = 64 / G;                 // columns per wave pass
-  const int lig = lane & (G - 1), col = lane / G;
-  const int ch0 = lig * LF;
-  const int nval = clampi(C - ch0, 0, LF);
-  for (int tb = wv * CPW; tb < T; tb += NW * CPW) {
-    const int t = tb + col;
-    const bool ok = t < T;
-    const int tw = (ok ? t : 0) >> 6;
-    const int tb_ = (ok ? t : 0) & 63;
-    uint64_t fm0 = 0;
-#pragma unroll 4
-    for (int i = 0; i < LF; ++i) {
-      if (i < nval) {
-        const uint64_t w = ld_mask(m0 + (int64_t)(ch0 + i) * W + tw);
-        fm0 |= ((w >> tb_) & 1ull) << i;
-      }
-    }
-    if (!ok) fm0 = 0;
-    FreqLoader<INT, LF> ld{&b, ok ? t : 0, ch0, nval, ok};
-    const uint64_t fm = st_core<INT, LF>(ld, fm0, lig, C, 1, nlev, sm);
-    uint64_t nb = ok ? (fm & ~fm0) : 0ull;
-    if (G == 1) {
-      // 64 consecutive columns of one word per channel: ballot per channel
-      if (__ballot(nb != 0) != 0) {
-        for (int i = 0; i < LF && i < C; ++i) {
-          const uint64_t word = __ballot((int)((nb >> i) & 1ull));
-          if (word != 0 && lane == 0) or_mask(m0 + (int64_t)i * W + (tb >> 6), word);
-        }
-      }
-    } else {
-      while (nb) {
-        const int i = __builtin_ctzll(nb);
-        nb &= nb - 1;
-        or_mask(m0 + (int64_t)(ch0 + i) * W + tw, 1ull << tb_);
-      }
+// Frequency layout: columns of C channels; LF channels per lane, G lanes per
+// column (LF = 16 or 32 with G = 1 for C <= 32, else LF = 32 and G = C/32 rounded
+// up to a power of two).  The block is walked in slabs of NW*64/G columns staged
+// in LDS (powers and the mask words covering the slab).
+struct FreqShape {
+  int LFc, G, cpw, cpi, stride, lig, colw, ch0, nval;
+  __device__ FreqShape(int C, int lane) {
+    LFc = C <= 16 ? 16 : 32;
+    G = 1;
+    while (G * LFc < C) G <<= 1;
+    cpw = 64 / G;
+    cpi = NW * cpw;
+    stride = cpi + 1;
+    lig = lane & (G - 1);
+    colw = lane / G;
+    ch0 = lig * LFc;
+    nval = clampi(C - ch0, 0, LFc);
+  }
+};
+
+template <bool INT, class SM>
+__device__ __forceinline__ void stage_slab(const DevBlock& b, SM& sm, const GLB uint64_t* m0, int W, int it0, int ncols, int wb,
+                           int nwl, int stride, bool powers) {
+  typedef typename PowT<INT>::T VT;
+  const int tid = threadIdx.x, C = b.C;
+  const FastDiv fw((uint32_t)nwl);
+  for (int i = tid; i < C * nwl; i += WG) {
+    const int c = (int)fw.div((uint32_t)i), j = i - c * nwl;
+    sm.u.f.w[i] = m0[(int64_t)c * W + wb + j];
+  }
+  if (powers) {
+    const int nch8 = (ncols + 7) >> 3;
+    const FastDiv f8((uint32_t)nch8);
+    for (int i = tid; i < C * nch8; i += WG) {
+      const int c = (int)f8.div((uint32_t)i), j = i - c * nch8;
+      VT v[8];
+      if (b.aligned && it0 + 8 * j + 8 <= b.T) load8v<INT>(b, c, it0 + 8 * j, v);
+      else load8<INT>(b, c, it0 + 8 * j, v);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sm.u.f.t[c * stride + 8 * j + q] = (typename TileOf<INT>::T)v[q];
     }
   }
 }
 
-template <bool INT>
-__device__ void phase_freq(const DevBlock& b, const DevParams& P, Smem& sm) {
+template <bool INT, int LF, class SM>
+__device__ __forceinline__ void phase_freq_l(const DevBlock& b, const DevParams& P, SM& sm) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
+  const int T = b.T, C = b.C;
+  const int W = (T + 63) >> 6;
+  GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
+  const int nlev = min(P.nl_f, ST_MAX_LEVELS);
+  const FreqShape fs(C, lane);
+  for (int it0 = 0; it0 < T; it0 += fs.cpi) {
+    const int ncols = min(fs.cpi, T - it0);
+    const int wb = it0 >> 6;
+    const int nwl = ((it0 + ncols - 1) >> 6) - wb + 1;
+    stage_slab<INT>(b, sm, m0, W, it0, ncols, wb, nwl, fs.stride, true);
+    __syncthreads();
+    const int col = wv * fs.cpw + fs.colw;
+    const int t = it0 + col;
+    const bool ok = col < ncols;
+    const int tt = ok ? t : it0;
+    const int wsel = (tt >> 6) - wb, bsel = tt & 63;
+    uint64_t fm0 = 0;
+#pragma unroll
+    for (int i = 0; i < LF; ++i)
+      if (i < fs.nval) fm0 |= ((sm.u.f.w[(fs.ch0 + i) * nwl + wsel] >> bsel) & 1ull) << i;
+    if (!ok) fm0 = 0;
+    TileLoader<INT, LF> ld{sm.u.f.t, fs.stride, ok ? col : 0, fs.ch0, fs.nval, ok};
+    const uint64_t fm = st_core<INT, LF>(ld, fm0, fs.lig, C, 1, nlev, sm);
+    uint64_t nb = ok ? (fm & ~fm0) : 0ull;
+    while (nb) {
+      const int i = __builtin_ctzll(nb);
+      nb &= nb - 1;
+      or_bit_lds(sm.u.f.w, (fs.ch0 + i) * nwl + wsel, bsel);
+    }
+    __syncthreads();
+    for (int i = tid; i < C * nwl; i += WG) {
+      const int c = i / nwl, j = i - c * nwl;
+      m0[(int64_t)c * W + wb + j] = sm.u.f.w[i];
+    }
+    __syncthreads();
+  }
+}
+
+// Integer input with exactly NC (16, 32 or 64) channels: one lane per column,
+// all NC channels in the lane, every loop bound known at compile time so only
+// full windows are summed and judged (no cross-lane traffic).
+template <int NC, class SM>
+__device__ __forceinline__ void col_fill(const uint16_t* tile, int stride, int col, bool ok, uint64_t fm,
+                                         uint32_t (&D)[NC]) {
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    const uint32_t p = tile[i * stride + col];
+    const bool live = ok && !((fm >> i) & 1ull);
+    D[i] = live ? p * 512u + 4u : 0u;
+    if ((i & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int NC, int M>
+__device__ __forceinline__ void col_rebuild(uint32_t (&D)[NC]) {
+  // D = S_1 -> S_{2^M}: step j sums windows of 2^(j+1) from halves 2^j
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const int h = 1 << j;
+#pragma unroll
+    for (int i = 0; i + 2 * h <= NC; ++i) D[i] += D[i + h];
+  }
+}
+
+template <int NC, int K, class SM>
+__device__ __forceinline__ void col_level(const uint16_t* tile, int stride, int col, bool ok, uint32_t (&D)[NC],
+                                          uint64_t& fm, bool& dirty, const SM& sm) {
+  constexpr int I = 1 << K;
+  if constexpr (I <= NC) {
+    if (dirty) {
+      col_fill<NC, SM>(tile, stride, col, ok, fm, D);
+      col_rebuild<NC, K - 1>(D);
+    }
+#pragma unroll
+    for (int i = 0; i + I <= NC; ++i) D[i] += D[i + I / 2];
+    const int32_t* Gk = sm.G[K];
+    unsigned long long any = 0;
+#pragma unroll
+    for (int i = 0; i + I <= NC; ++i) {
+      any |= __ballot((int32_t)D[i] > Gk[(D[i] >> 2) & 127u]);
+      if ((i & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+    }
+    if (any == 0) {
+      dirty = false;
+      return;
+    }
+    uint64_t wf = 0;
+#pragma unroll
+    for (int i = 0; i + I <= NC; ++i) {
+      wf |= (uint64_t)(((int32_t)D[i] > Gk[(D[i] >> 2) & 127u]) ? 1u : 0u) << i;
+      if ((i & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+    }
+    if (!ok) wf = 0;
+    uint64_t nb = wf;
+#pragma unroll
+    for (int d = 1; d < I; d <<= 1) nb |= nb << d;
+    nb &= lowmask(NC);
+    const uint64_t changed = nb & ~fm;
+    fm |= nb;
+    dirty = __ballot(changed != 0) != 0;
+  }
+}
+
+template <int NC, class SM>
+__device__ __forceinline__ uint64_t st_col(const uint16_t* tile, int stride, int col, bool ok, uint64_t fm, int nlev, const SM& sm) {
+  uint32_t D[NC];
+  col_fill<NC, SM>(tile, stride, col, ok, fm, D);
+  bool dirty = false;
+#define LOF_CLEVEL(K) \
+  if (K < nlev) col_level<NC, K>(tile, stride, col, ok, D, fm, dirty, sm);
+  LOF_CLEVEL(1)
+  LOF_CLEVEL(2)
+  LOF_CLEVEL(3)
+  LOF_CLEVEL(4)
+  LOF_CLEVEL(5)
+  LOF_CLEVEL(6)
+#undef LOF_CLEVEL
+  return fm;
+}
+
+template <int NC, class SM>
+__device__ __forceinline__ void phase_freq_col(const DevBlock& b, const DevParams& P, SM& sm) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
+  const int T = b.T, C = NC;
+  const int W = (T + 63) >> 6;
+  GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
+  const int nlev = min(P.nl_f, ST_MAX_LEVELS);
+  constexpr int cpi = NW * 64, stride = cpi + 1;
+  for (int it0 = 0; it0 < T; it0 += cpi) {
+    const int ncols = min(cpi, T - it0);
+    const int wb = it0 >> 6;
+    const int nwl = ((it0 + ncols - 1) >> 6) - wb + 1;
+    stage_slab<true>(b, sm, m0, W, it0, ncols, wb, nwl, stride, true);
+    __syncthreads();
+    const int col = wv * 64 + lane;
+    const bool ok = col < ncols;
+    const int wsel = wv;   // it0 is a multiple of 64: wave w owns word wb + w
+    uint64_t fm0 = 0;
+    if (wsel < nwl) {
+#pragma unroll 4
+      for (int i = 0; i < NC; ++i) fm0 |= ((sm.u.f.w[i * nwl + wsel] >> lane) & 1ull) << i;
+    }
+    if (!ok) fm0 = 0;
+    const uint64_t fm = st_col<NC>(sm.u.f.t, stride, ok ? col : 0, ok, fm0, nlev, sm);
+    const uint64_t nb = ok ? (fm & ~fm0) : 0ull;
+    if (__ballot(nb != 0) != 0) {
+      // one wave owns one word per channel: rebuild it with ballots
+#pragma unroll
+      for (int i = 0; i < NC; ++i) {
+        const unsigned long long word = __ballot((int)((nb >> i) & 1ull));
+        if (lane == 0 && word != 0) sm.u.f.w[i * nwl + wsel] |= word;
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < C * nwl; i += WG) {
+      const int c = i / nwl, j = i - c * nwl;
+      m0[(int64_t)c * W + wb + j] = sm.u.f.w[i];
+    }
+    __syncthreads();
+  }
+}
+
+template <bool INT, class SM>
+__device__ __forceinline__ void phase_freq(const DevBlock& b, const DevParams& P, SM& sm) {
   const int C = b.C;
   if (C <= 1 || P.nl_f <= 1) return;
-  if (C <= 16) phase_freq_l<INT, 16>(b, P, sm, 1);
-  else if (C <= 32) phase_freq_l<INT, 32>(b, P, sm, 1);
-  else {
-    int G = 1;
-    while (G * 64 < C) G <<= 1;
-    phase_freq_l<INT, 64>(b, P, sm, G);
+  if constexpr (INT) {
+    if (C == 64) return phase_freq_col<64>(b, P, sm);
+    if (C == 32) return phase_freq_col<32>(b, P, sm);
+    if (C == 16) return phase_freq_col<16>(b, P, sm);
   }
+  if (C <= 16) phase_freq_l<INT, 16>(b, P, sm);
+  else phase_freq_l<INT, 32>(b, P, sm);
 }
 
 // ===================================================================== phase C: SIR
@@ -597,12 +935,14 @@ struct SirSum {
 
 template <int L>
 __device__ __forceinline__ SirSum sir_lane_summary(uint64_t bits, int nval, int num, int den) {
+  const uint64_t vm = lowmask(nval);
+  const uint64_t fb = bits & vm, ub = ~bits & vm;
+  const int nmd = num - den;
   int W = 0, mn = BIG, mx = -BIG;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     mn = min(mn, W);
-    const int w = (i < nval) ? (((bits >> i) & 1ull) ? num : num - den) : 0;
-    W += w;
+    W += (int)((fb >> i) & 1ull) * num + (int)((ub >> i) & 1ull) * nmd;
     mx = max(mx, W);
   }
   return SirSum{W, mn, mx};
@@ -640,31 +980,35 @@ __device__ __forceinline__ void sir_group_scan(const SirSum s, int lig, int G, i
 template <int L>
 __device__ __forceinline__ uint64_t sir_lane_apply(uint64_t bits, int nval, int num, int den, int Wstart,
                                                    int pmin_in, int smax_in) {
+  const uint64_t vm = lowmask(nval);
+  const uint64_t fb = bits & vm, ub = ~bits & vm;
+  const int nmd = num - den;
   int PM[L];
   int W = Wstart, pm = pmin_in;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     pm = min(pm, W);
     PM[i] = pm;
-    W += (i < nval) ? (((bits >> i) & 1ull) ? num : num - den) : 0;
+    W += (int)((fb >> i) & 1ull) * num + (int)((ub >> i) & 1ull) * nmd;
   }
   int sm = smax_in;
-  uint64_t out = 0;
+  uint32_t lo = 0, hi = 0;
 #pragma unroll
   for (int i = L - 1; i >= 0; --i) {
     sm = max(sm, W);
-    if (sm - PM[i] >= 0) out |= 1ull << i;
-    W -= (i < nval) ? (((bits >> i) & 1ull) ? num : num - den) : 0;
+    const uint32_t h = (sm >= PM[i]) ? 1u : 0u;
+    if (i < 32) lo |= h << i; else hi |= h << (i - 32);
+    W -= (int)((fb >> i) & 1ull) * num + (int)((ub >> i) & 1ull) * nmd;
   }
-  return out & lowmask(nval);
+  return ((uint64_t)lo | ((uint64_t)hi << 32)) & vm;
 }
 
-template <int L>
-__device__ void phase_sir_time(const DevBlock& b, const DevParams& P, Smem& sm) {
+template <int L, class SM>
+__device__ __forceinline__ void phase_sir_time(const DevBlock& b, const DevParams& P, SM& sm) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int T = b.T, C = b.C;
   const int W = (T + 63) >> 6;
-  uint64_t* m0 = P.maskw + b.mask_off;
+  GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
   const int num = P.eta_num, den = P.eta_den;
   if (T <= 64 * L) {
     int G = 1;
@@ -673,7 +1017,7 @@ __device__ void phase_sir_time(const DevBlock& b, const DevParams& P, Smem& sm) 
     for (int rb = wv * R; rb < C; rb += NW * R) {
       const int row = rb + grp;
       const bool ok = row < C;
-      uint64_t* rp = m0 + (int64_t)(ok ? row : 0) * W;
+      GLB uint64_t* rp = m0 + (int64_t)(ok ? row : 0) * W;
       const int nval = ok ? clampi(T - lig * L, 0, L) : 0;
       const uint64_t bits = ok ? (get_bits(rp, W, lig * L, L) & lowmask(nval)) : 0ull;
       const bool any = __ballot(bits != 0) != 0;
@@ -689,7 +1033,7 @@ __device__ void phase_sir_time(const DevBlock& b, const DevParams& P, Smem& sm) 
     const int nseg = (T + SIR_SEG - 1) / SIR_SEG;
     int(*seg)[3] = sm.u.c.seg[wv];
     for (int row = wv; row < C; row += NW) {
-      uint64_t* rp = m0 + (int64_t)row * W;
+      GLB uint64_t* rp = m0 + (int64_t)row * W;
       bool any = false;
       for (int s = 0; s < nseg; ++s) {
         const int q = s * SIR_SEG + lane * L;
@@ -742,76 +1086,70 @@ __device__ void phase_sir_time(const DevBlock& b, const DevParams& P, Smem& sm) 
   }
 }
 
-template <int LF>
-__device__ void phase_sir_freq_l(const DevBlock& b, const DevParams& P, Smem& sm, int G) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+template <int LF, class SM>
+__device__ __forceinline__ void phase_sir_freq_l(const DevBlock& b, const DevParams& P, SM& sm) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
   const int T = b.T, C = b.C;
   const int W = (T + 63) >> 6;
-  uint64_t* m0 = P.maskw + b.mask_off;
+  GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
   const int num = P.eta_num, den = P.eta_den;
-  const int CPW = 64 / G;
-  const int lig = lane & (G - 1), col = lane / G;
-  const int ch0 = lig * LF;
-  const int nval = clampi(C - ch0, 0, LF);
-  for (int tb = wv * CPW; tb < T; tb += NW * CPW) {
-    const int t = tb + col;
-    const bool ok = t < T;
-    const int tw = (ok ? t : 0) >> 6;
-    const int tb_ = (ok ? t : 0) & 63;
+  const FreqShape fs(C, lane);
+  for (int it0 = 0; it0 < T; it0 += fs.cpi) {
+    const int ncols = min(fs.cpi, T - it0);
+    const int wb = it0 >> 6;
+    const int nwl = ((it0 + ncols - 1) >> 6) - wb + 1;
+    stage_slab<true>(b, sm, m0, W, it0, ncols, wb, nwl, fs.stride, false);
+    __syncthreads();
+    const int col = wv * fs.cpw + fs.colw;
+    const int t = it0 + col;
+    const bool ok = col < ncols;
+    const int tt = ok ? t : it0;
+    const int wsel = (tt >> 6) - wb, bsel = tt & 63;
     uint64_t bits = 0;
-#pragma unroll 4
-    for (int i = 0; i < LF; ++i) {
-      if (i < nval) {
-        const uint64_t w = ld_mask(m0 + (int64_t)(ch0 + i) * W + tw);
-        bits |= ((w >> tb_) & 1ull) << i;
-      }
-    }
+#pragma unroll
+    for (int i = 0; i < LF; ++i)
+      if (i < fs.nval) bits |= ((sm.u.f.w[(fs.ch0 + i) * nwl + wsel] >> bsel) & 1ull) << i;
     if (!ok) bits = 0;
-    if (__ballot(bits != 0) == 0 && num < den) continue;
-    const int nv = ok ? nval : 0;
-    const SirSum s = sir_lane_summary<LF>(bits, nv, num, den);
-    int base = 0, pmin = BIG, smax = -BIG, gt, gn, gx;
-    if (G > 1) sir_group_scan(s, lig, G, base, pmin, smax, gt, gn, gx);
-    const uint64_t out = sir_lane_apply<LF>(bits, nv, num, den, base, pmin, smax);
-    uint64_t nb = out & ~bits;
-    if (G == 1) {
-      if (__ballot(nb != 0) != 0) {
-        for (int i = 0; i < LF && i < C; ++i) {
-          const uint64_t word = __ballot((int)((nb >> i) & 1ull));
-          if (word != 0 && lane == 0) or_mask(m0 + (int64_t)i * W + (tb >> 6), word);
-        }
-      }
-    } else {
+    const bool work = (__ballot(bits != 0) != 0) || num >= den;
+    if (work) {
+      const int nv = ok ? fs.nval : 0;
+      const SirSum s = sir_lane_summary<LF>(bits, nv, num, den);
+      int base = 0, pmin = BIG, smax = -BIG, gt, gn, gx;
+      if (fs.G > 1) sir_group_scan(s, fs.lig, fs.G, base, pmin, smax, gt, gn, gx);
+      const uint64_t out = sir_lane_apply<LF>(bits, nv, num, den, base, pmin, smax);
+      uint64_t nb = out & ~bits;
       while (nb) {
         const int i = __builtin_ctzll(nb);
         nb &= nb - 1;
-        or_mask(m0 + (int64_t)(ch0 + i) * W + tw, 1ull << tb_);
+        or_bit_lds(sm.u.f.w, (fs.ch0 + i) * nwl + wsel, bsel);
       }
     }
+    __syncthreads();
+    for (int i = tid; i < C * nwl; i += WG) {
+      const int c = i / nwl, j = i - c * nwl;
+      m0[(int64_t)c * W + wb + j] = sm.u.f.w[i];
+    }
+    __syncthreads();
   }
 }
 
-__device__ void phase_sir_freq(const DevBlock& b, const DevParams& P, Smem& sm) {
+template <class SM>
+__device__ __forceinline__ void phase_sir_freq(const DevBlock& b, const DevParams& P, SM& sm) {
   const int C = b.C;
   if (C <= 1) return;
-  if (C <= 16) phase_sir_freq_l<16>(b, P, sm, 1);
-  else if (C <= 32) phase_sir_freq_l<32>(b, P, sm, 1);
-  else {
-    int G = 1;
-    while (G * 64 < C) G <<= 1;
-    phase_sir_freq_l<64>(b, P, sm, G);
-  }
+  if (C <= 16) phase_sir_freq_l<16>(b, P, sm);
+  else phase_sir_freq_l<32>(b, P, sm);
 }
 
 // ===================================================================== phase D
 // History flagger (Sec. 4.1): per channel, the mean of this block's unflagged
 // samples against mean + history_sensitivity * stddev of the committed means.
-template <bool INT>
-__device__ void phase_history(const DevBlock& b, const DevParams& P, Smem& sm) {
+template <bool INT, class SM>
+__device__ __forceinline__ void phase_history(const DevBlock& b, const DevParams& P, SM& sm) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int T = b.T, C = b.C;
   const int W = (T + 63) >> 6;
-  const uint64_t* m0 = P.maskw + b.mask_off;
+  const GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
   for (int i = tid; i < MAXC / 32; i += WG) sm.rowflag[i] = 0u;
   if (b.stream_id < 0) {
     __syncthreads();
@@ -823,12 +1161,15 @@ __device__ void phase_history(const DevBlock& b, const DevParams& P, Smem& sm) {
     unsigned long long su = 0;
     double sd = 0.0;
     int cnt = 0;
+    const bool fast = b.aligned && (T & 7) == 0;
     for (int c = lane; c < nch; c += 64) {
       const int t0 = c * 8;
       const uint64_t w = ld_mask(m0 + (int64_t)row * W + (t0 >> 6));
       const uint32_t fb = (uint32_t)(w >> (t0 & 63)) & 0xffu;
       VT v[8];
-      const int nv = load8<INT>(b, row, t0, v);
+      int nv = 8;
+      if (fast) load8v<INT>(b, row, t0, v);
+      else nv = load8<INT>(b, row, t0, v);
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         if (j < nv && !((fb >> j) & 1u)) {
@@ -855,16 +1196,16 @@ __device__ void phase_history(const DevBlock& b, const DevParams& P, Smem& sm) {
     const int64_t idx = (int64_t)s * P.maxC + row;
     const int cnt = sm.u.c.rcnt[row];
     if (cnt == 0) {
-      P.pvalid[idx] = 0;
+      gp<uint8_t>(P.pvalid)[idx] = 0;
       continue;
     }
     const double cur = sm.u.c.rsum[row] / (double)cnt;
-    const int L = P.rcount[idx];
+    const int L = gp<const int32_t>(P.rcount)[idx];
     bool flag = false;
     double pushv = cur;
     if (L >= P.Hmin) {
-      const int head = P.rhead[idx];
-      const double* ring = P.ring + idx * P.H;
+      const int head = gp<const int32_t>(P.rhead)[idx];
+      const GLB double* ring = gp<const double>(P.ring) + idx * P.H;
       double acc = 0.0;
       for (int j = 0; j < L; ++j) {
         int k = head - L + j;
@@ -884,32 +1225,34 @@ __device__ void phase_history(const DevBlock& b, const DevParams& P, Smem& sm) {
       flag = P.literal ? (cur >= thr) : (cur > thr);
       if (flag) pushv = thr;
     }
-    P.pend[idx] = pushv;
-    P.pvalid[idx] = 1;
+    gp<double>(P.pend)[idx] = pushv;
+    gp<uint8_t>(P.pvalid)[idx] = 1;
     if (flag) atomicOr(&sm.rowflag[row >> 5], 1u << (row & 31));
   }
   __syncthreads();
 }
 
 // final flags = SIR mask OR history rows; one byte per sample
-__device__ void phase_write(const DevBlock& b, const DevParams& P, Smem& sm) {
+template <class SM>
+__device__ __forceinline__ void phase_write(const DevBlock& b, const DevParams& P, SM& sm) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int T = b.T, C = b.C;
   const int W = (T + 63) >> 6;
-  const uint64_t* m0 = P.maskw + b.mask_off;
+  const GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
   const int nch = (T + 15) >> 4;
-  const int64_t items = (int64_t)C * nch;
+  const uint32_t items = (uint32_t)C * (uint32_t)nch;
+  const FastDiv fd((uint32_t)nch);
   unsigned long long nfl = 0;
-  for (int64_t it = tid; it < items; it += WG) {
-    const int row = (int)(it / nch);
-    const int t0 = (int)(it - (int64_t)row * nch) * 16;
+  for (uint32_t it = tid; it < items; it += WG) {
+    const int row = (int)fd.div(it);
+    const int t0 = (int)(it - (uint32_t)row * (uint32_t)nch) * 16;
     const uint64_t w = ld_mask(m0 + (int64_t)row * W + (t0 >> 6));
     uint32_t fb = (uint32_t)(w >> (t0 & 63)) & 0xffffu;
     if ((sm.rowflag[row >> 5] >> (row & 31)) & 1u) fb = 0xffffu;
     const int nv = min(16, T - t0);
     fb &= (nv >= 16) ? 0xffffu : ((1u << nv) - 1u);
     nfl += (unsigned long long)__builtin_popcount(fb);
-    uint8_t* fp = b.flags + (int64_t)row * b.fstride + t0;
+    GLB uint8_t* fp = gp<uint8_t>(b.flags) + (int64_t)row * b.fstride + t0;
     if (b.faligned && nv == 16) {
       uint32_t o[4];
 #pragma unroll
@@ -917,7 +1260,7 @@ __device__ void phase_write(const DevBlock& b, const DevParams& P, Smem& sm) {
         const uint32_t nib = (fb >> (4 * j)) & 0xfu;
         o[j] = (nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21);
       }
-      *(uint4*)fp = make_uint4(o[0], o[1], o[2], o[3]);
+      *(GLB u32x4*)fp = u32x4{o[0], o[1], o[2], o[3]};
     } else {
       for (int j = 0; j < nv; ++j) fp[j] = (uint8_t)((fb >> j) & 1u);
     }
@@ -931,26 +1274,34 @@ __device__ void phase_write(const DevBlock& b, const DevParams& P, Smem& sm) {
     for (int w = 0; w < NW; ++w) tot += sm.red_u[0][w];
     int hr = 0;
     for (int i = 0; i < MAXC / 32; ++i) hr += __builtin_popcount(sm.rowflag[i]);
-    double* st = (double*)((char*)P.stats + (int64_t)b.out_idx * (int64_t)(18 * 8 + 16));
+    GLB double* st = (GLB double*)(gp<char>(P.stats) + (int64_t)b.out_idx * (int64_t)(18 * 8 + 16));
     st[0] = sm.median;
     st[1] = sm.sigma;
     const int nT = max(P.nl_t, P.nl_f);
     for (int k = 0; k < 16; ++k) st[2 + k] = k < nT ? sm.T[k] : 0.0;
-    *(long long*)(st + 18) = (long long)tot;
-    *(int*)(st + 19) = hr;
-    *((int*)(st + 19) + 1) = 0;
+    *(GLB long long*)(st + 18) = (long long)tot;
+    *(GLB int*)(st + 19) = hr;
+    *((GLB int*)(st + 19) + 1) = 0;
   }
 }
 
 // ===================================================================== kernels
+// Phase boundary: every wave's mask stores must be visible to the other waves of
+// the workgroup.  All waves of a workgroup run on one CU and share its
+// write-through L1, so a workgroup-scope fence plus barrier suffices (a
+// device-scope fence would write back the whole L2).
 __device__ __forceinline__ void phase_sync() {
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+#ifndef LOF_WAVES_PER_EU
+#define LOF_WAVES_PER_EU 4
+#endif
 template <bool INT, int L>
-__global__ __launch_bounds__(WG) void lof_flag_kernel(const DevBlock* __restrict__ blocks, DevParams P) {
-  __shared__ Smem sm;
+__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_flag_kernel(const DevBlock* __restrict__ blocks, DevParams P) {
+  __shared__ SmemT<INT> sm;
   const DevBlock b = blocks[blockIdx.x];
   phase_stats<INT>(b, P, sm);
   phase_time<INT, L>(b, P, sm);
