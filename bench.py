@@ -52,16 +52,17 @@ def _gen_range(args):
     return b1 - b0
 
 
-def make_config1(nb: int, workers: int):
+def make_config1(nb: int, workers: int, start_method: str = "fork"):
     """All blocks of the 48-station second, generated in parallel; returns
-    (array view, shared-memory handle)."""
+    (array view, shared-memory handle).  Use start_method="spawn" once the GPU
+    runtime is initialised in this process."""
     from multiprocessing import shared_memory
     shm = shared_memory.SharedMemory(create=True, size=nb * C * T * 2)
     chunks = []
     step = max(1, nb // (workers * 8))
     for b0 in range(0, nb, step):
         chunks.append((shm.name, nb, b0, min(nb, b0 + step)))
-    ctx = mp.get_context("fork")
+    ctx = mp.get_context(start_method)
     with ctx.Pool(workers) as pool:
         for _ in pool.imap_unordered(_gen_range, chunks):
             pass
