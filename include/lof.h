@@ -63,6 +63,11 @@ typedef enum {
                                             values it staged (same enqueue)          */
 #define LOF_OPT_LITERAL_HISTORY_TIE 0x2u /* history flags when cur >= thr (the Sec. 4.1
                                             listing's else-branch) instead of cur > thr */
+#define LOF_OPT_GRAPH 0x4u               /* keep the launches of the last block table in
+                                            a hipGraph and replay it when lof_flag_blocks
+                                            is called again with the identical table and
+                                            stats pointer (no descriptor upload, one
+                                            graph launch)                                 */
 
 #define LOF_MAX_LEVELS 16
 #define LOF_MAX_CHANNELS 1024
@@ -74,8 +79,8 @@ typedef struct {
   double p;                    /* factor base (Sec. 2.1), 1.5                         */
   double sensitivity;          /* Sec. 2.1, 1.0                                       */
   int32_t n_levels;            /* SumThreshold iterations along time, I = 1..2^(n-1)
-                                  (Sec. 2.1: 7-10); a level with I > extent is skipped;
-                                  1..LOF_MAX_LEVELS-1                                 */
+                                  (Sec. 2.1: 7-10 typical); 1..7 (windows up to 64 are
+                                  supported); a level with I > extent is skipped      */
   int32_t n_levels_freq;       /* iterations along frequency; -1 = same as n_levels  */
   int32_t sir_eta_num;         /* SIR eta = num/den (Sec. 2.2: 20 % -> 1/5);          */
   int32_t sir_eta_den;         /* num = 0 disables SIR; 0 <= num <= den, den <= 1024  */
@@ -106,6 +111,19 @@ typedef struct {
                                   [0, max_streams), or -1 for no history; an id may
                                   appear at most once per call                       */
 } lof_block;
+
+/* Launch tuning.  Blocks are grouped by input kind (0 = complex int8, 1 = float
+ * types) and time-length bucket (T <= 1024, <= 2048, <= 3072, <= 4096, larger);
+ * time_lanes[kind][bucket] is the number of consecutive time samples each GPU
+ * lane holds (32, 48 or 64; a row must fit 64 lanes unless the value is 64).
+ * persistent = 1 launches a chip-sized grid whose workgroups take blocks from a
+ * work counter (largest first) instead of one workgroup per block. */
+#define LOF_TUNE_BUCKETS 5
+typedef struct {
+  int32_t time_lanes[2][LOF_TUNE_BUCKETS];
+  int32_t persistent;
+  int32_t _reserved;
+} lof_tuning;
 
 typedef struct {
   double median;               /* block median (Sec. 2.1)                            */
@@ -156,6 +174,20 @@ lof_status lof_history_update(lof_ctx* ctx, const int32_t* stream_ids, int32_t n
  * and tests. */
 lof_status lof_history_export(lof_ctx* ctx, double* values, int32_t* counts,
                               double* staged, uint8_t* staged_valid, void* hip_stream);
+
+/* Reads / replaces the launch tuning of ctx (see lof_tuning).  Results never
+ * depend on it.  Errors: LOF_ERR_INVALID for NULL pointers or values outside
+ * the allowed set. */
+lof_status lof_get_tuning(const lof_ctx* ctx, lof_tuning* out);
+lof_status lof_set_tuning(lof_ctx* ctx, const lof_tuning* tuning);
+
+/* Autotuner: times every allowed time_lanes value for each (kind, bucket) that
+ * occurs in `blocks`, and the two launch modes, on these blocks, and keeps the
+ * fastest in ctx (synchronous; `reps` timed launches per candidate).  It writes
+ * the blocks' flag outputs but stages no history (tuning runs ignore stream
+ * ids).  *out (host, nullable) receives the chosen tuning. */
+lof_status lof_autotune(lof_ctx* ctx, const lof_block* blocks, int32_t n_blocks, void* hip_stream,
+                        int32_t reps, lof_tuning* out);
 
 /* Frees the context.  The caller must have synchronised every stream used with
  * it.  NULL is a no-op. */

@@ -17,10 +17,13 @@ LOF_OK, LOF_ERR_INVALID, LOF_ERR_NOMEM, LOF_ERR_DEVICE, LOF_ERR_CAPACITY = 0, -1
 LOF_CI8, LOF_C64, LOF_F32, LOF_C64_AMP = 0, 1, 2, 3
 LOF_OPT_AUTOCOMMIT = 0x1
 LOF_OPT_LITERAL_HISTORY_TIE = 0x2
+LOF_OPT_GRAPH = 0x4
 LOF_MAX_LEVELS = 16
+LOF_TUNE_BUCKETS = 5
 
 EXPORTED = ("lof_default_params", "lof_create", "lof_flag_blocks", "lof_history_update",
-            "lof_history_export", "lof_destroy", "lof_last_error")
+            "lof_history_export", "lof_get_tuning", "lof_set_tuning", "lof_autotune", "lof_destroy",
+            "lof_last_error")
 
 
 class LofParams(ctypes.Structure):
@@ -69,6 +72,14 @@ class LofBlockStats(ctypes.Structure):
     ]
 
 
+class LofTuning(ctypes.Structure):
+    _fields_ = [
+        ("time_lanes", (ctypes.c_int32 * LOF_TUNE_BUCKETS) * 2),
+        ("persistent", ctypes.c_int32),
+        ("_reserved", ctypes.c_int32),
+    ]
+
+
 STATS_BYTES = ctypes.sizeof(LofBlockStats)
 
 _lib = None
@@ -99,6 +110,13 @@ def load() -> ctypes.CDLL:
     L.lof_history_export.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p]
     L.lof_history_export.restype = ctypes.c_int
+    L.lof_get_tuning.argtypes = [ctypes.c_void_p, ctypes.POINTER(LofTuning)]
+    L.lof_get_tuning.restype = ctypes.c_int
+    L.lof_set_tuning.argtypes = [ctypes.c_void_p, ctypes.POINTER(LofTuning)]
+    L.lof_set_tuning.restype = ctypes.c_int
+    L.lof_autotune.argtypes = [ctypes.c_void_p, ctypes.POINTER(LofBlock), ctypes.c_int32, ctypes.c_void_p,
+                               ctypes.c_int32, ctypes.POINTER(LofTuning)]
+    L.lof_autotune.restype = ctypes.c_int
     L.lof_destroy.argtypes = [ctypes.c_void_p]
     L.lof_destroy.restype = ctypes.c_int
     L.lof_last_error.argtypes = [ctypes.c_void_p]

@@ -35,11 +35,19 @@ struct Slot {
   DevBlock* d_desc = nullptr;
   DevBlock* h_desc = nullptr;     // pinned
   uint64_t* d_mask = nullptr;
+  int* d_counter = nullptr;       // persistent-launch work counters, one per variant
   hipEvent_t ev = nullptr;
   bool used = false;
 };
 
-int time_class(int T) { return T <= 2048 ? 0 : (T <= 3072 ? 1 : 2); }
+int time_bucket(int T) { return T <= 1024 ? 0 : (T <= 2048 ? 1 : (T <= 3072 ? 2 : (T <= 4096 ? 3 : 4))); }
+int lanes_index(int L) { return L == 32 ? 0 : (L == 48 ? 1 : 2); }
+bool lanes_allowed(int L, int bucket) {
+  static const int maxT[LOF_TUNE_BUCKETS] = {1024, 2048, 3072, 4096, 1 << 30};
+  if (L != 32 && L != 48 && L != 64) return false;
+  return L == 64 || 64 * L >= maxT[bucket];
+}
+constexpr int NVAR = 6;   // kernel variants: (integer, float) x (32, 48, 64 lanes)
 
 size_t elem_size(int dtype) { return dtype == LOF_CI8 ? 2 : (dtype == LOF_F32 ? 4 : 8); }
 
@@ -55,6 +63,17 @@ struct lof_ctx {
   uint8_t* pvalid = nullptr;
   Slot slot[NSLOT];
   int next = 0;
+  lof_tuning tune;
+  int occ[NVAR] = {0, 0, 0, 0, 0, 0};   // resident workgroups per CU of each variant
+  int n_cu = 0;
+  // hipGraph cache (LOF_OPT_GRAPH): the last block table, its graph and its slot
+  Slot gslot;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<lof_block> gsig;
+  void* gstats = nullptr;
+  bool gvalid = false;
   size_t mask_words = 0;
   std::vector<int32_t> seen;     // per stream: last call that named it
   int32_t call_no = 0;
@@ -125,8 +144,174 @@ lof_status fail(lof_ctx* c, lof_status s, const char* msg) {
 
 }  // namespace
 
-extern "C" {
 
+namespace {
+
+typedef void (*KernFn)(const DevBlock*, int, int*, DevParams);
+const void* kernel_of(int v) {
+  switch (v) {
+    case 0: return (const void*)lofk::lof_flag_kernel<true, 32>;
+    case 1: return (const void*)lofk::lof_flag_kernel<true, 48>;
+    case 2: return (const void*)lofk::lof_flag_kernel<true, 64>;
+    case 3: return (const void*)lofk::lof_flag_kernel<false, 32>;
+    case 4: return (const void*)lofk::lof_flag_kernel<false, 48>;
+    default: return (const void*)lofk::lof_flag_kernel<false, 64>;
+  }
+}
+
+void launch_variant(int v, dim3 grid, hipStream_t st, const DevBlock* dd, int n, int* counter, const DevParams& P) {
+  dim3 blk(lofk::WG);
+  switch (v) {
+    case 0: hipLaunchKernelGGL((lofk::lof_flag_kernel<true, 32>), grid, blk, 0, st, dd, n, counter, P); break;
+    case 1: hipLaunchKernelGGL((lofk::lof_flag_kernel<true, 48>), grid, blk, 0, st, dd, n, counter, P); break;
+    case 2: hipLaunchKernelGGL((lofk::lof_flag_kernel<true, 64>), grid, blk, 0, st, dd, n, counter, P); break;
+    case 3: hipLaunchKernelGGL((lofk::lof_flag_kernel<false, 32>), grid, blk, 0, st, dd, n, counter, P); break;
+    case 4: hipLaunchKernelGGL((lofk::lof_flag_kernel<false, 48>), grid, blk, 0, st, dd, n, counter, P); break;
+    default: hipLaunchKernelGGL((lofk::lof_flag_kernel<false, 64>), grid, blk, 0, st, dd, n, counter, P); break;
+  }
+}
+
+void free_slot(Slot& s) {
+  if (s.d_desc) (void)hipFree(s.d_desc);
+  if (s.h_desc) (void)hipHostFree(s.h_desc);
+  if (s.d_mask) (void)hipFree(s.d_mask);
+  if (s.d_counter) (void)hipFree(s.d_counter);
+  if (s.ev) (void)hipEventDestroy(s.ev);
+  s = Slot();
+}
+
+bool alloc_slot(Slot& s, int max_blocks, size_t mask_words) {
+  return hipMalloc(&s.d_desc, sizeof(DevBlock) * max_blocks) == hipSuccess &&
+         hipHostMalloc(&s.h_desc, sizeof(DevBlock) * max_blocks, hipHostMallocDefault) == hipSuccess &&
+         hipMalloc(&s.d_mask, sizeof(uint64_t) * mask_words) == hipSuccess &&
+         hipMalloc(&s.d_counter, sizeof(int) * NVAR) == hipSuccess &&
+         hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) == hipSuccess;
+}
+
+void default_tuning(lof_tuning* t) {
+  std::memset(t, 0, sizeof(*t));
+  for (int k = 0; k < 2; ++k) {
+    t->time_lanes[k][0] = 32;
+    t->time_lanes[k][1] = 32;
+    t->time_lanes[k][2] = 48;
+    t->time_lanes[k][3] = 64;
+    t->time_lanes[k][4] = 64;
+  }
+  t->persistent = 0;
+}
+
+bool tuning_ok(const lof_tuning* t) {
+  if (!t || (t->persistent != 0 && t->persistent != 1)) return false;
+  for (int k = 0; k < 2; ++k)
+    for (int b = 0; b < LOF_TUNE_BUCKETS; ++b)
+      if (!lanes_allowed(t->time_lanes[k][b], b)) return false;
+  return true;
+}
+
+int variant_of(const lof_tuning& t, const lof_block& b) {
+  const int kind = b.dtype == LOF_CI8 ? 0 : 1;
+  return kind * 3 + lanes_index(t.time_lanes[kind][time_bucket(b.n_times)]);
+}
+
+// validation of one call (all-or-nothing); fills *samples
+lof_status validate(lof_ctx* c, const lof_block* blocks, int32_t n, bool check_ids) {
+  if (n > c->prm.max_blocks_per_call) return fail(c, LOF_ERR_CAPACITY, "more blocks than max_blocks_per_call");
+  c->call_no++;
+  if (c->call_no == 0x7fffffff) {
+    std::fill(c->seen.begin(), c->seen.end(), -1);
+    c->call_no = 1;
+  }
+  int64_t samples = 0;
+  size_t words = 0;
+  for (int i = 0; i < n; ++i) {
+    const lof_block& b = blocks[i];
+    if (!b.data || !b.flags) return fail(c, LOF_ERR_INVALID, "block data or flags pointer is NULL");
+    if (b.n_channels < 1 || b.n_times < 1) return fail(c, LOF_ERR_INVALID, "block shape must be >= 1 x 1");
+    if (b.n_channels > LOF_MAX_CHANNELS) return fail(c, LOF_ERR_INVALID, "more than 1024 channels");
+    if (b.n_channels > c->prm.max_channels) return fail(c, LOF_ERR_CAPACITY, "n_channels > max_channels");
+    if (b.n_times > MAX_TIMES) return fail(c, LOF_ERR_INVALID, "more than 262144 times");
+    if ((int64_t)b.n_channels * b.n_times > LOF_MAX_BLOCK_SAMPLES)
+      return fail(c, LOF_ERR_INVALID, "block larger than 2^23 samples");
+    if (b.data_row_stride < b.n_times || b.flag_row_stride < b.n_times)
+      return fail(c, LOF_ERR_INVALID, "row stride smaller than n_times");
+    if (b.dtype < LOF_CI8 || b.dtype > LOF_C64_AMP) return fail(c, LOF_ERR_INVALID, "unknown dtype");
+    if (b.stream_id < -1 || b.stream_id >= c->prm.max_streams)
+      return fail(c, LOF_ERR_INVALID, "stream_id out of range");
+    if (check_ids && b.stream_id >= 0) {
+      if (c->seen[b.stream_id] == c->call_no) return fail(c, LOF_ERR_INVALID, "stream_id repeated in one call");
+      c->seen[b.stream_id] = c->call_no;
+    }
+    samples += (int64_t)b.n_channels * b.n_times;
+    words += (size_t)b.n_channels * (size_t)((b.n_times + 63) / 64);
+  }
+  if (samples > c->prm.max_samples_per_call)
+    return fail(c, LOF_ERR_CAPACITY, "more samples than max_samples_per_call");
+  if (words > c->mask_words) return fail(c, LOF_ERR_CAPACITY, "mask scratch too small");
+  return LOF_OK;
+}
+
+// descriptor table in s.h_desc: variant groups, largest block first; counts[v]
+void build_table(lof_ctx* c, const lof_tuning& t, const lof_block* blocks, int32_t n, Slot& s, int* counts,
+                 bool history) {
+  int* order = c->order.data();
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::sort(order, order + n, [&](int a, int bb) {
+    const int va = variant_of(t, blocks[a]), vb = variant_of(t, blocks[bb]);
+    if (va != vb) return va < vb;
+    const int64_t sa = (int64_t)blocks[a].n_channels * blocks[a].n_times;
+    const int64_t sb = (int64_t)blocks[bb].n_channels * blocks[bb].n_times;
+    if (sa != sb) return sa > sb;
+    return a < bb;
+  });
+  int64_t moff = 0;
+  for (int v = 0; v < NVAR; ++v) counts[v] = 0;
+  for (int j = 0; j < n; ++j) {
+    const int i = order[j];
+    const lof_block& b = blocks[i];
+    DevBlock& d = s.h_desc[j];
+    d.data = b.data;
+    d.flags = b.flags;
+    d.dstride = b.data_row_stride;
+    d.fstride = b.flag_row_stride;
+    d.C = b.n_channels;
+    d.T = b.n_times;
+    d.dtype = b.dtype;
+    d.stream_id = history ? b.stream_id : -1;
+    d.mask_off = moff;
+    d.out_idx = i;
+    const size_t es = elem_size(b.dtype);
+    d.aligned = (((uintptr_t)b.data % 16) == 0 && ((size_t)b.data_row_stride * es) % 16 == 0) ? 1 : 0;
+    d.faligned = (((uintptr_t)b.flags % 16) == 0 && (b.flag_row_stride % 16) == 0) ? 1 : 0;
+    d.pad = 0;
+    moff += (int64_t)b.n_channels * ((b.n_times + 63) / 64);
+    counts[variant_of(t, b)]++;
+  }
+}
+
+// kernels of one call on stream st (descriptors already on the device in s)
+void enqueue(lof_ctx* c, const lof_tuning& t, Slot& s, const int* counts, int n, void* stats, hipStream_t st,
+             bool autocommit) {
+  const DevParams P = dev_params(c, s.d_mask, stats);
+  if (t.persistent) hipLaunchKernelGGL(lofk::lof_zero_kernel, dim3(1), dim3(64), 0, st, s.d_counter, NVAR);
+  int off = 0;
+  for (int v = 0; v < NVAR; ++v) {
+    const int cnt = counts[v];
+    if (!cnt) continue;
+    const DevBlock* dd = s.d_desc + off;
+    if (t.persistent) {
+      const int cap = std::max(1, c->occ[v]) * std::max(1, c->n_cu);
+      launch_variant(v, dim3(std::min(cnt, cap)), st, dd, cnt, s.d_counter + v, P);
+    } else {
+      launch_variant(v, dim3(cnt), st, dd, cnt, nullptr, P);
+    }
+    off += cnt;
+  }
+  if (autocommit) hipLaunchKernelGGL(lofk::lof_commit_desc_kernel, dim3(n), dim3(256), 0, st, s.d_desc, n, P);
+}
+
+}  // namespace
+
+extern "C" {
 lof_status lof_default_params(lof_params* p) {
   if (!p) return LOF_ERR_INVALID;
   std::memset(p, 0, sizeof(*p));
@@ -148,15 +333,15 @@ lof_status lof_default_params(lof_params* p) {
   return LOF_OK;
 }
 
+
 lof_status lof_destroy(lof_ctx* c) {
   if (!c) return LOF_OK;
   DevGuard g(c->dev);
-  for (auto& s : c->slot) {
-    if (s.d_desc) (void)hipFree(s.d_desc);
-    if (s.h_desc) (void)hipHostFree(s.h_desc);
-    if (s.d_mask) (void)hipFree(s.d_mask);
-    if (s.ev) (void)hipEventDestroy(s.ev);
-  }
+  for (auto& s : c->slot) free_slot(s);
+  free_slot(c->gslot);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->ring) (void)hipFree(c->ring);
   if (c->rcount) (void)hipFree(c->rcount);
   if (c->rhead) (void)hipFree(c->rhead);
@@ -188,6 +373,7 @@ lof_status lof_create(const lof_params* params, int hip_device, lof_ctx** out) {
   }
   c->prm = *params;
   c->dev = hip_device;
+  default_tuning(&c->tune);
   DevGuard g(hip_device);
   const int64_t SC = (int64_t)params->max_streams * params->max_channels;
   bool ok = hipMalloc(&c->ring, sizeof(double) * SC * params->history_len) == hipSuccess &&
@@ -205,13 +391,17 @@ lof_status lof_create(const lof_params* params, int hip_device, lof_ctx** out) {
   // mask scratch: one u64 word per 64 samples of a row, rows rounded up
   c->mask_words = (size_t)(params->max_samples_per_call / 64) +
                   (size_t)params->max_blocks_per_call * (size_t)params->max_channels + 64;
-  for (int i = 0; ok && i < NSLOT; ++i) {
-    Slot& s = c->slot[i];
-    ok = hipMalloc(&s.d_desc, sizeof(DevBlock) * params->max_blocks_per_call) == hipSuccess &&
-         hipHostMalloc(&s.h_desc, sizeof(DevBlock) * params->max_blocks_per_call, hipHostMallocDefault) ==
-             hipSuccess &&
-         hipMalloc(&s.d_mask, sizeof(uint64_t) * c->mask_words) == hipSuccess &&
-         hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; ok && i < NSLOT; ++i) ok = alloc_slot(c->slot[i], params->max_blocks_per_call, c->mask_words);
+  if (ok && (params->options & LOF_OPT_GRAPH)) {
+    ok = alloc_slot(c->gslot, params->max_blocks_per_call, c->mask_words) &&
+         hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
+  }
+  if (ok) {
+    hipDeviceProp_t prop;
+    ok = hipGetDeviceProperties(&prop, hip_device) == hipSuccess;
+    c->n_cu = ok ? prop.multiProcessorCount : 0;
+    for (int v = 0; ok && v < NVAR; ++v)
+      ok = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c->occ[v], kernel_of(v), lofk::WG, 0) == hipSuccess;
   }
   if (ok) ok = hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
@@ -233,110 +423,153 @@ lof_status lof_flag_blocks(lof_ctx* c, const lof_block* blocks, int32_t n, void*
   if (n < 0) return fail(c, LOF_ERR_INVALID, "n_blocks < 0");
   if (n == 0) return LOF_OK;
   if (!blocks) return fail(c, LOF_ERR_INVALID, "blocks is NULL");
-  if (n > c->prm.max_blocks_per_call) return fail(c, LOF_ERR_CAPACITY, "more blocks than max_blocks_per_call");
-  // ---- validation (all-or-nothing)
-  c->call_no++;
-  if (c->call_no == 0x7fffffff) {
-    std::fill(c->seen.begin(), c->seen.end(), -1);
-    c->call_no = 1;
-  }
-  int64_t samples = 0;
-  size_t words = 0;
-  for (int i = 0; i < n; ++i) {
-    const lof_block& b = blocks[i];
-    if (!b.data || !b.flags) return fail(c, LOF_ERR_INVALID, "block data or flags pointer is NULL");
-    if (b.n_channels < 1 || b.n_times < 1) return fail(c, LOF_ERR_INVALID, "block shape must be >= 1 x 1");
-    if (b.n_channels > LOF_MAX_CHANNELS) return fail(c, LOF_ERR_INVALID, "more than 1024 channels");
-    if (b.n_channels > c->prm.max_channels) return fail(c, LOF_ERR_CAPACITY, "n_channels > max_channels");
-    if (b.n_times > MAX_TIMES) return fail(c, LOF_ERR_INVALID, "more than 262144 times");
-    if ((int64_t)b.n_channels * b.n_times > LOF_MAX_BLOCK_SAMPLES)
-      return fail(c, LOF_ERR_INVALID, "block larger than 2^23 samples");
-    if (b.data_row_stride < b.n_times || b.flag_row_stride < b.n_times)
-      return fail(c, LOF_ERR_INVALID, "row stride smaller than n_times");
-    if (b.dtype < LOF_CI8 || b.dtype > LOF_C64_AMP) return fail(c, LOF_ERR_INVALID, "unknown dtype");
-    if (b.stream_id < -1 || b.stream_id >= c->prm.max_streams)
-      return fail(c, LOF_ERR_INVALID, "stream_id out of range");
-    if (b.stream_id >= 0) {
-      if (c->seen[b.stream_id] == c->call_no) return fail(c, LOF_ERR_INVALID, "stream_id repeated in one call");
-      c->seen[b.stream_id] = c->call_no;
-    }
-    samples += (int64_t)b.n_channels * b.n_times;
-    words += (size_t)b.n_channels * (size_t)((b.n_times + 63) / 64);
-  }
-  if (samples > c->prm.max_samples_per_call) return fail(c, LOF_ERR_CAPACITY, "more samples than max_samples_per_call");
-  if (words > c->mask_words) return fail(c, LOF_ERR_CAPACITY, "mask scratch too small");
-
+  const lof_status vs = validate(c, blocks, n, true);
+  if (vs != LOF_OK) return vs;
   DevGuard g(c->dev);
   hipStream_t st = (hipStream_t)hip_stream;
+  const bool autocommit = (c->prm.options & LOF_OPT_AUTOCOMMIT) != 0;
+  int counts[NVAR];
+
+  if (c->prm.options & LOF_OPT_GRAPH) {
+    Slot& s = c->gslot;
+    const bool same = c->gvalid && (int32_t)c->gsig.size() == n && c->gstats == (void*)stats &&
+                      std::memcmp(c->gsig.data(), blocks, sizeof(lof_block) * n) == 0;
+    if (!same) {
+      // rebuild: the previous replay must be done before its table is replaced
+      if (s.used && hipEventSynchronize(s.ev) != hipSuccess) return fail(c, LOF_ERR_DEVICE, "graph wait failed");
+      if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+      if (c->graph) (void)hipGraphDestroy(c->graph);
+      c->gexec = nullptr;
+      c->graph = nullptr;
+      c->gvalid = false;
+      build_table(c, c->tune, blocks, n, s, counts, true);
+      if (hipMemcpy(s.d_desc, s.h_desc, sizeof(DevBlock) * n, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(c, LOF_ERR_DEVICE, "descriptor upload failed");
+      if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(c, LOF_ERR_DEVICE, "graph capture failed");
+      enqueue(c, c->tune, s, counts, n, stats, c->cap_stream, autocommit);
+      if (hipStreamEndCapture(c->cap_stream, &c->graph) != hipSuccess ||
+          hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, LOF_ERR_DEVICE, "graph instantiation failed");
+      }
+      c->gsig.assign(blocks, blocks + n);
+      c->gstats = (void*)stats;
+      c->gvalid = true;
+    } else if (s.used) {
+      // replays share the graph's scratch: order them on the device
+      if (hipStreamWaitEvent(st, s.ev, 0) != hipSuccess) return fail(c, LOF_ERR_DEVICE, "stream wait failed");
+    }
+    if (hipGraphLaunch(c->gexec, st) != hipSuccess) return fail(c, LOF_ERR_DEVICE, "graph launch failed");
+    if (hipEventRecord(s.ev, st) != hipSuccess) return fail(c, LOF_ERR_DEVICE, "hipEventRecord failed");
+    s.used = true;
+    return LOF_OK;
+  }
+
   Slot& s = c->slot[c->next];
   c->next = (c->next + 1) % NSLOT;
   if (s.used) {
     // the slot's previous call must be done before its table and scratch are reused
     if (hipEventSynchronize(s.ev) != hipSuccess) return fail(c, LOF_ERR_DEVICE, "hipEventSynchronize failed");
   }
-  // ---- descriptors: kernel variant groups (integer/float x time class), largest first
-  int* order = c->order.data();
-  for (int i = 0; i < n; ++i) order[i] = i;
-  auto variant = [&](int i) {
-    const lof_block& b = blocks[i];
-    return (b.dtype == LOF_CI8 ? 0 : 3) + time_class(b.n_times);
-  };
-  std::sort(order, order + n, [&](int a, int bb) {
-    const int va = variant(a), vb = variant(bb);
-    if (va != vb) return va < vb;
-    const int64_t sa = (int64_t)blocks[a].n_channels * blocks[a].n_times;
-    const int64_t sb = (int64_t)blocks[bb].n_channels * blocks[bb].n_times;
-    if (sa != sb) return sa > sb;
-    return a < bb;
-  });
-  int64_t moff = 0;
-  int counts[6] = {0, 0, 0, 0, 0, 0};
-  for (int j = 0; j < n; ++j) {
-    const int i = order[j];
-    const lof_block& b = blocks[i];
-    DevBlock& d = s.h_desc[j];
-    d.data = b.data;
-    d.flags = b.flags;
-    d.dstride = b.data_row_stride;
-    d.fstride = b.flag_row_stride;
-    d.C = b.n_channels;
-    d.T = b.n_times;
-    d.dtype = b.dtype;
-    d.stream_id = b.stream_id;
-    d.mask_off = moff;
-    d.out_idx = i;
-    const size_t es = elem_size(b.dtype);
-    d.aligned = (((uintptr_t)b.data % 16) == 0 && ((size_t)b.data_row_stride * es) % 16 == 0) ? 1 : 0;
-    d.faligned = (((uintptr_t)b.flags % 16) == 0 && (b.flag_row_stride % 16) == 0) ? 1 : 0;
-    d.pad = 0;
-    moff += (int64_t)b.n_channels * ((b.n_times + 63) / 64);
-    counts[variant(i)]++;
-  }
+  build_table(c, c->tune, blocks, n, s, counts, true);
   if (hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(DevBlock) * n, hipMemcpyHostToDevice, st) != hipSuccess)
     return fail(c, LOF_ERR_DEVICE, "descriptor upload failed");
-  const DevParams P = dev_params(c, s.d_mask, stats);
-  int off = 0;
-  for (int v = 0; v < 6; ++v) {
-    const int cnt = counts[v];
-    if (!cnt) continue;
-    const DevBlock* dd = s.d_desc + off;
-    dim3 grid(cnt), blk(lofk::WG);
-    switch (v) {
-      case 0: hipLaunchKernelGGL((lofk::lof_flag_kernel<true, 32>), grid, blk, 0, st, dd, P); break;
-      case 1: hipLaunchKernelGGL((lofk::lof_flag_kernel<true, 48>), grid, blk, 0, st, dd, P); break;
-      case 2: hipLaunchKernelGGL((lofk::lof_flag_kernel<true, 64>), grid, blk, 0, st, dd, P); break;
-      case 3: hipLaunchKernelGGL((lofk::lof_flag_kernel<false, 32>), grid, blk, 0, st, dd, P); break;
-      case 4: hipLaunchKernelGGL((lofk::lof_flag_kernel<false, 48>), grid, blk, 0, st, dd, P); break;
-      default: hipLaunchKernelGGL((lofk::lof_flag_kernel<false, 64>), grid, blk, 0, st, dd, P); break;
-    }
-    off += cnt;
-  }
-  if (c->prm.options & LOF_OPT_AUTOCOMMIT) {
-    hipLaunchKernelGGL(lofk::lof_commit_desc_kernel, dim3(n), dim3(256), 0, st, s.d_desc, n, P);
-  }
+  enqueue(c, c->tune, s, counts, n, stats, st, autocommit);
   if (hipGetLastError() != hipSuccess) return fail(c, LOF_ERR_DEVICE, "kernel launch failed");
   if (hipEventRecord(s.ev, st) != hipSuccess) return fail(c, LOF_ERR_DEVICE, "hipEventRecord failed");
   s.used = true;
+  return LOF_OK;
+}
+
+lof_status lof_get_tuning(const lof_ctx* c, lof_tuning* out) {
+  if (!c || !out) return LOF_ERR_INVALID;
+  *out = c->tune;
+  return LOF_OK;
+}
+
+lof_status lof_set_tuning(lof_ctx* c, const lof_tuning* t) {
+  if (!c) return LOF_ERR_INVALID;
+  if (!tuning_ok(t)) return fail(c, LOF_ERR_INVALID, "tuning values outside the allowed set");
+  c->tune = *t;
+  c->gvalid = false;   // a cached graph was built with the old tuning
+  return LOF_OK;
+}
+
+lof_status lof_autotune(lof_ctx* c, const lof_block* blocks, int32_t n, void* hip_stream, int32_t reps,
+                        lof_tuning* out) {
+  if (!c) return LOF_ERR_INVALID;
+  if (n < 0 || reps < 1) return fail(c, LOF_ERR_INVALID, "n < 0 or reps < 1");
+  if (n > 0 && !blocks) return fail(c, LOF_ERR_INVALID, "blocks is NULL");
+  if (n > 0) {
+    const lof_status vs = validate(c, blocks, n, false);
+    if (vs != LOF_OK) return vs;
+  }
+  DevGuard g(c->dev);
+  hipStream_t st = (hipStream_t)hip_stream;
+  // wait for every slot: tuning uses slot 0 synchronously
+  for (auto& s : c->slot)
+    if (s.used && hipEventSynchronize(s.ev) != hipSuccess) return fail(c, LOF_ERR_DEVICE, "slot wait failed");
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(c, LOF_ERR_DEVICE, "event creation failed");
+  Slot& s = c->slot[0];
+  lof_tuning best = c->tune;
+  auto time_run = [&](const lof_tuning& t, const std::vector<lof_block>& sub, float* ms) -> bool {
+    int counts[NVAR];
+    const int m = (int)sub.size();
+    build_table(c, t, sub.data(), m, s, counts, false);
+    if (hipMemcpy(s.d_desc, s.h_desc, sizeof(DevBlock) * m, hipMemcpyHostToDevice) != hipSuccess) return false;
+    enqueue(c, t, s, counts, m, nullptr, st, false);   // warm-up
+    if (hipEventRecord(e0, st) != hipSuccess) return false;
+    for (int r = 0; r < reps; ++r) enqueue(c, t, s, counts, m, nullptr, st, false);
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return false;
+    return hipEventElapsedTime(ms, e0, e1) == hipSuccess;
+  };
+  bool ok = true;
+  // 1) time layout per (kind, bucket) present in the table, one-workgroup-per-block launches
+  for (int kind = 0; ok && kind < 2; ++kind) {
+    for (int b = 0; ok && b < LOF_TUNE_BUCKETS; ++b) {
+      std::vector<lof_block> sub;
+      for (int i = 0; i < n; ++i)
+        if ((blocks[i].dtype == LOF_CI8 ? 0 : 1) == kind && time_bucket(blocks[i].n_times) == b)
+          sub.push_back(blocks[i]);
+      if (sub.empty()) continue;
+      float best_ms = 1e30f;
+      for (int L : {32, 48, 64}) {
+        if (!lanes_allowed(L, b)) continue;
+        lof_tuning t = best;
+        t.time_lanes[kind][b] = L;
+        t.persistent = 0;
+        float ms = 0.0f;
+        ok = time_run(t, sub, &ms);
+        if (ok && ms < best_ms) {
+          best_ms = ms;
+          best.time_lanes[kind][b] = L;
+        }
+      }
+    }
+  }
+  // 2) launch mode on the whole table
+  if (ok && n > 0) {
+    std::vector<lof_block> all(blocks, blocks + n);
+    float ms0 = 0.0f, ms1 = 0.0f;
+    lof_tuning t = best;
+    t.persistent = 0;
+    ok = time_run(t, all, &ms0);
+    t.persistent = 1;
+    if (ok) ok = time_run(t, all, &ms1);
+    if (ok) best.persistent = ms1 < ms0 ? 1 : 0;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!ok) {
+    (void)hipGetLastError();
+    return fail(c, LOF_ERR_DEVICE, "autotune run failed");
+  }
+  c->tune = best;
+  c->gvalid = false;
+  if (out) *out = best;
   return LOF_OK;
 }
 

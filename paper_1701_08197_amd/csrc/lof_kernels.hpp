@@ -1299,10 +1299,9 @@ __device__ __forceinline__ void phase_sync() {
 #ifndef LOF_WAVES_PER_EU
 #define LOF_WAVES_PER_EU 4
 #endif
-template <bool INT, int L>
-__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_flag_kernel(const DevBlock* __restrict__ blocks, DevParams P) {
-  __shared__ SmemT<INT> sm;
-  const DevBlock b = blocks[blockIdx.x];
+
+template <bool INT, int L, class SM>
+__device__ __forceinline__ void flag_one_block(const DevBlock& b, const DevParams& P, SM& sm) {
   phase_stats<INT>(b, P, sm);
   phase_time<INT, L>(b, P, sm);
   phase_sync();
@@ -1316,6 +1315,36 @@ __global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_flag_kernel(const De
   }
   phase_history<INT>(b, P, sm);
   phase_write(b, P, sm);
+}
+
+// One workgroup per block (counter == nullptr), or a persistent grid whose
+// workgroups take the next block index from a device counter until the table
+// (ordered largest first) is exhausted.
+template <bool INT, int L>
+__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_flag_kernel(const DevBlock* __restrict__ blocks, int nb,
+                                                                        int* counter, DevParams P) {
+  __shared__ SmemT<INT> sm;
+  if (counter == nullptr) {
+    const DevBlock b = blocks[blockIdx.x];
+    flag_one_block<INT, L>(b, P, sm);
+    return;
+  }
+  __shared__ int cur;
+  for (;;) {
+    if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
+    __syncthreads();
+    const int bi = cur;
+    __syncthreads();
+    if (bi >= nb) break;
+    const DevBlock b = blocks[bi];
+    flag_one_block<INT, L>(b, P, sm);
+    __syncthreads();
+  }
+}
+
+// zero a few device ints (work counters) without a memset node
+__global__ void lof_zero_kernel(int* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
 // Commit staged history values (Sec. 4.1 addToHistory) of a list of streams.

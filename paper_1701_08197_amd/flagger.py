@@ -126,6 +126,24 @@ class Flagger:
             _stream_handle(stream)))
         return {"values": vals, "counts": cnt, "staged": staged, "staged_valid": valid}
 
+    def get_tuning(self) -> N.LofTuning:
+        t = N.LofTuning()
+        self._check(self._L.lof_get_tuning(self._h, ctypes.byref(t)))
+        return t
+
+    def set_tuning(self, t: N.LofTuning) -> None:
+        self._check(self._L.lof_set_tuning(self._h, ctypes.byref(t)))
+
+    def autotune(self, blocks, stream=None, reps: int = 3) -> N.LofTuning:
+        """lof_autotune on a list of Block (or LofBlock); returns the chosen tuning."""
+        n = len(blocks)
+        arr = (N.LofBlock * max(1, n))()
+        for i, b in enumerate(blocks):
+            arr[i] = b if isinstance(b, N.LofBlock) else b.to_c()
+        t = N.LofTuning()
+        self._check(self._L.lof_autotune(self._h, arr, n, _stream_handle(stream), reps, ctypes.byref(t)))
+        return t
+
     def close(self) -> None:
         if getattr(self, "_h", None):
             self._L.lof_destroy(self._h)

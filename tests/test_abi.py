@@ -39,7 +39,8 @@ def test_struct_layouts_match_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    structs = {"lof_params": N.LofParams, "lof_block": N.LofBlock, "lof_block_stats": N.LofBlockStats}
+    structs = {"lof_params": N.LofParams, "lof_block": N.LofBlock, "lof_block_stats": N.LofBlockStats,
+               "lof_tuning": N.LofTuning}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lof.h"', "int main(void){"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
