@@ -104,6 +104,129 @@ def cpu_baseline(cores: int, target_cpu_s: float):
                       f"{sum(cpu):.1f} s of CPU in {wall:.1f} s wall on {cores} processes"}
 
 
+# ------------------------------------------------------------------ config 2
+def _gen_cfg2(args):
+    b, C, T = args
+    return b, synth.f32_power_block(synth.rng_for(2, b), C, T)
+
+
+def run_batched(args, cores):
+    """4096 uneven float32 blocks: one launch per block vs one batched call
+    (default tuning, autotuned, and hipGraph replay of the tuned call)."""
+    import torch
+    import paper_1701_08197_amd as P
+    from paper_1701_08197_amd import _native as NAT
+    nb = args.blocks2
+    shapes = synth.config2_shapes()[:nb]
+    # rows padded to 16 elements so every row starts 16-byte aligned
+    offs, strides, tot, samples = [], [], 0, 0
+    for C_, T_ in shapes:
+        st_ = (T_ + 15) // 16 * 16
+        offs.append(tot)
+        strides.append(st_)
+        tot += C_ * st_
+        samples += C_ * T_
+    data = torch.empty(tot, dtype=torch.float32, device="cuda")
+    flags = torch.empty(tot, dtype=torch.uint8, device="cuda")
+    t_gen = time.perf_counter()
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        for b, x in pool.imap_unordered(_gen_cfg2, [(b, C_, T_) for b, (C_, T_) in enumerate(shapes)], chunksize=4):
+            C_, T_ = x.shape
+            data[offs[b]:offs[b] + C_ * strides[b]].view(C_, strides[b])[:, :T_].copy_(torch.from_numpy(x))
+    t_gen = time.perf_counter() - t_gen
+    arr = (NAT.LofBlock * nb)()
+    for b, (C_, T_) in enumerate(shapes):
+        blk = arr[b]
+        blk.data = data[offs[b]:].data_ptr()
+        blk.flags = flags[offs[b]:].data_ptr()
+        blk.data_row_stride = strides[b]
+        blk.flag_row_stride = strides[b]
+        blk.n_channels = C_
+        blk.n_times = T_
+        blk.dtype = NAT.LOF_F32
+        blk.stream_id = b
+    base = dict(max_streams=nb, max_channels=256, max_blocks_per_call=nb, max_samples_per_call=tot)
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    fl = P.Flagger(P.default_params(**base))
+    one = (NAT.LofBlock * 1)()
+
+    def per_block():
+        for b in range(nb):
+            one[0] = arr[b]
+            if fl.flag_blocks_raw(one, 1, sh) != 0:
+                raise RuntimeError("flag failed")
+    t_pb = timed(per_block, 1)
+    t_batch = timed(lambda: fl.flag_blocks_raw(arr, nb, sh), args.steps)
+    tune = fl.autotune(list(arr), stream=sh, reps=1)
+    t_tuned = timed(lambda: fl.flag_blocks_raw(arr, nb, sh), args.steps)
+    fl.close()
+    fg = P.Flagger(P.default_params(options=P.LOF_OPT_GRAPH, **base))
+    fg.set_tuning(tune)
+    t_graph = timed(lambda: fg.flag_blocks_raw(arr, nb, sh), args.steps)
+    fg.close()
+    gs = lambda t: round(samples / t / 1e9, 3)
+    return {"metric": "flagged Gsamples/s, batched uneven blocks", "workload": "4096 float32 power blocks, "
+            "C in {16,64,256}, T uniform in [768,12288], 1/f bandpass drift + RFI mix",
+            "blocks": nb, "samples": samples, "unit": "Gsamples/s",
+            "per_block_launches": gs(t_pb), "batched_default": gs(t_batch), "batched_autotuned": gs(t_tuned),
+            "graph_replay_autotuned": gs(t_graph),
+            "alg_GBps_graph": round(samples * 5 / t_graph / 1e9, 1),
+            "tuning": {"time_lanes": [list(tune.time_lanes[0]), list(tune.time_lanes[1])],
+                       "persistent": tune.persistent},
+            "gen_s": round(t_gen, 1)}
+
+
+# ------------------------------------------------------------------ config 4
+def _gen_cfg4(args):
+    st, sb = args
+    return st, sb, synth.config4_block(st, 0, sb)
+
+
+def run_serve(args, cores):
+    """48 stations, 16-64 subbands each, Poisson arrivals (mean 1 s per station),
+    continuous batching over a fixed device arena; sweep of arrival speed-ups."""
+    import torch
+    from paper_1701_08197_amd.serve import Service, latency_summary
+    subs = synth.config4_subbands()
+    pool = {}
+    ctx = mp.get_context("fork")
+    jobs = [(st, sb) for st, n in enumerate(subs) for sb in range(n)]
+    with ctx.Pool(cores) as p:
+        for st, sb, x in p.imap_unordered(_gen_cfg4, jobs, chunksize=8):
+            pool[(st, sb)] = torch.from_numpy(x).cuda()
+    points = []
+    for speedup in [float(v) for v in args.speedups.split(",")]:
+        obs = max(8.0, args.serve_wall * speedup)
+        arrivals = [(t, st, k) for (t, st, k) in synth.config4_arrivals(obs)]
+        svc = Service(len(subs), 64, n_slots=args.slots, C=C, T=T)
+        t0 = time.perf_counter()
+        done = svc.run(arrivals, lambda st, k: [pool[(st, sb)] for sb in range(subs[st])], speedup=speedup)
+        wall = time.perf_counter() - t0
+        warm = sorted(done, key=lambda r: r.arrival)[len(done) // 4:]
+        summ = latency_summary(warm, C, T, wall, DEADLINE_S)
+        summ["admitted_gsamples_per_s"] = round(sum(len(r.slots) for r in done) * C * T / wall / 1e9, 3)
+        summ.update({"speedup": speedup, "observation_s": obs})
+        points.append({k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()})
+        svc.close()
+    ok = [p for p in points if p["p99_ms"] <= DEADLINE_S * 1e3]
+    return {"metric": "streaming: admitted Gsamples/s and p50/p99 block latency vs real-time deadline",
+            "workload": "48 stations x 16-64 subbands x 64 ch x 3072 t complex int8, Poisson arrivals (1 s)",
+            "arena_slots": args.slots, "points": points,
+            "max_speedup_meeting_deadline": max((p["speedup"] for p in ok), default=None)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +236,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--workers", type=int, default=0)
+    ap.add_argument("--workload", choices=["second", "batched", "serve"], default="second",
+                    help="second: the 48-station second (default); batched: 4096 uneven float blocks; "
+                         "serve: streaming service sweep")
+    ap.add_argument("--blocks2", type=int, default=4096)
+    ap.add_argument("--slots", type=int, default=4096)
+    ap.add_argument("--speedups", default="10,50,100,200,300")
+    ap.add_argument("--serve-wall", type=float, default=3.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the blocks are independent and "
@@ -122,6 +252,12 @@ def main():
     cores = len(os.sched_getaffinity(0))
     cores = min(cores, 16)
     workers = args.workers or cores
+    if args.workload == "batched":
+        print(json.dumps(run_batched(args, workers)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(run_serve(args, workers)), flush=True)
+        return
     nb = args.blocks
     t_gen = time.perf_counter()
     host, shm = make_config1(nb, workers)

@@ -78,3 +78,14 @@ def test_defaults_and_invalid_params_rejected_without_device():
     assert L.lof_flag_blocks(None, None, 0, None, None) == N.LOF_ERR_INVALID
     assert L.lof_history_update(None, None, 0, None) == N.LOF_ERR_INVALID
     assert L.lof_destroy(None) == N.LOF_OK
+
+
+def test_service_descriptor_view_matches_struct():
+    """The streaming service writes descriptor tables through a numpy view."""
+    import numpy as np
+    from paper_1701_08197_amd import _native as N
+    from paper_1701_08197_amd.serve import BLOCK_DTYPE
+    names = ["data", "flags", "dstride", "fstride", "C", "T", "dtype", "sid"]
+    for (cname, _), nname in zip(N.LofBlock._fields_, names):
+        assert BLOCK_DTYPE.fields[nname][1] == getattr(N.LofBlock, cname).offset
+    assert BLOCK_DTYPE.itemsize == np.dtype(np.uint8).itemsize * 48
