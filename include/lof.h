@@ -116,8 +116,9 @@ typedef struct {
  * types) and time-length bucket (T <= 1024, <= 2048, <= 3072, <= 4096, larger);
  * time_lanes[kind][bucket] is the number of consecutive time samples each GPU
  * lane holds (32, 48 or 64; a row must fit 64 lanes unless the value is 64).
- * persistent = 1 launches a chip-sized grid whose workgroups take blocks from a
- * work counter (largest first) instead of one workgroup per block. */
+ * persistent = 1 launches each phase kernel as a chip-sized grid whose
+ * workgroups take (block, chunk) items from a work counter (largest block
+ * first) instead of one workgroup per item. */
 #define LOF_TUNE_BUCKETS 5
 typedef struct {
   int32_t time_lanes[2][LOF_TUNE_BUCKETS];

@@ -96,6 +96,12 @@ def load() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise FileNotFoundError(f"{LIB_PATH} is missing: build it with paper_1701_08197_amd.build.build()")
+    # torch ships its own HIP runtime; load it first so that liblof binds to the
+    # same libamdhip64 (two HIP runtimes in one process do not share the device)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     L.lof_default_params.argtypes = [ctypes.POINTER(LofParams)]
     L.lof_default_params.restype = ctypes.c_int

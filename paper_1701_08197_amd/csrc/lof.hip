@@ -4,12 +4,15 @@
 // flagger Sec. 4.1; one independent block per station, polarisation and subband,
 // Sec. 4.1 domain decomposition).
 //
-// The host validates every block (all-or-nothing), groups blocks by the kernel
-// variant their time length needs, orders each group by decreasing size so the
-// largest blocks start first, uploads one descriptor table and launches one
-// kernel per group on the caller's stream.  No allocation happens after
-// lof_create: descriptor tables and mask scratch live in a small ring of slots,
-// each slot guarded by an event so that calls on different streams can overlap.
+// The host validates every block (all-or-nothing), groups blocks by input kind
+// and by the time layout their length needs, orders each group by decreasing
+// size so the largest blocks start first, uploads one descriptor table and
+// launches one kernel per phase on the caller's stream: statistics per block,
+// then SumThreshold time / frequency, SIR time / frequency and the history + flag
+// write, each over (block, chunk) work items.  No allocation happens after
+// lof_create: descriptor tables, per-block statistics and mask scratch live in a
+// small ring of slots, each slot guarded by an event so that calls on different
+// streams can overlap.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,6 +24,7 @@
 #include "lof.h"
 #include "lof_kernels.hpp"
 
+using lofk::BlockState;
 using lofk::DevBlock;
 using lofk::DevParams;
 
@@ -31,11 +35,14 @@ constexpr int MAX_TIMES = lofk::SIR_SEG * lofk::SIR_MAX_SEGS;   // 262144
 
 thread_local const char* g_create_err = "no error";
 
+constexpr int NCOUNTER = 32;      // persistent-launch work counters per call (<= 18 launches)
+
 struct Slot {
   DevBlock* d_desc = nullptr;
   DevBlock* h_desc = nullptr;     // pinned
   uint64_t* d_mask = nullptr;
-  int* d_counter = nullptr;       // persistent-launch work counters, one per variant
+  BlockState* d_state = nullptr;
+  int* d_counter = nullptr;       // persistent-launch work counters, one per launch
   hipEvent_t ev = nullptr;
   bool used = false;
 };
@@ -47,7 +54,11 @@ bool lanes_allowed(int L, int bucket) {
   if (L != 32 && L != 48 && L != 64) return false;
   return L == 64 || 64 * L >= maxT[bucket];
 }
-constexpr int NVAR = 6;   // kernel variants: (integer, float) x (32, 48, 64 lanes)
+constexpr int NVAR = 6;   // time layouts: (integer, float) x (32, 48, 64 lanes)
+
+// kernels, for occupancy lookups
+enum KernId { K_STATS = 0, K_TIME = 2, K_FREQ = 8, K_SIRT = 10, K_SIRF = 13, K_FINAL = 14, NKERN = 16 };
+int variant_lanes(int v) { return v % 3 == 0 ? 32 : (v % 3 == 1 ? 48 : 64); }
 
 size_t elem_size(int dtype) { return dtype == LOF_CI8 ? 2 : (dtype == LOF_F32 ? 4 : 8); }
 
@@ -64,7 +75,7 @@ struct lof_ctx {
   Slot slot[NSLOT];
   int next = 0;
   lof_tuning tune;
-  int occ[NVAR] = {0, 0, 0, 0, 0, 0};   // resident workgroups per CU of each variant
+  int occ[NKERN] = {};   // resident workgroups per CU of each kernel
   int n_cu = 0;
   // hipGraph cache (LOF_OPT_GRAPH): the last block table, its graph and its slot
   Slot gslot;
@@ -95,7 +106,7 @@ struct DevGuard {
   }
 };
 
-DevParams dev_params(const lof_ctx* c, uint64_t* mask, void* stats) {
+DevParams dev_params(const lof_ctx* c, uint64_t* mask, BlockState* state, void* stats) {
   DevParams P;
   P.start = c->prm.start_threshold;
   P.p = c->prm.p;
@@ -115,6 +126,7 @@ DevParams dev_params(const lof_ctx* c, uint64_t* mask, void* stats) {
   P.pend = c->pend;
   P.pvalid = c->pvalid;
   P.maskw = mask;
+  P.bstate = state;
   P.stats = stats;
   return P;
 }
@@ -147,27 +159,24 @@ lof_status fail(lof_ctx* c, lof_status s, const char* msg) {
 
 namespace {
 
-typedef void (*KernFn)(const DevBlock*, int, int*, DevParams);
-const void* kernel_of(int v) {
-  switch (v) {
-    case 0: return (const void*)lofk::lof_flag_kernel<true, 32>;
-    case 1: return (const void*)lofk::lof_flag_kernel<true, 48>;
-    case 2: return (const void*)lofk::lof_flag_kernel<true, 64>;
-    case 3: return (const void*)lofk::lof_flag_kernel<false, 32>;
-    case 4: return (const void*)lofk::lof_flag_kernel<false, 48>;
-    default: return (const void*)lofk::lof_flag_kernel<false, 64>;
-  }
-}
-
-void launch_variant(int v, dim3 grid, hipStream_t st, const DevBlock* dd, int n, int* counter, const DevParams& P) {
-  dim3 blk(lofk::WG);
-  switch (v) {
-    case 0: hipLaunchKernelGGL((lofk::lof_flag_kernel<true, 32>), grid, blk, 0, st, dd, n, counter, P); break;
-    case 1: hipLaunchKernelGGL((lofk::lof_flag_kernel<true, 48>), grid, blk, 0, st, dd, n, counter, P); break;
-    case 2: hipLaunchKernelGGL((lofk::lof_flag_kernel<true, 64>), grid, blk, 0, st, dd, n, counter, P); break;
-    case 3: hipLaunchKernelGGL((lofk::lof_flag_kernel<false, 32>), grid, blk, 0, st, dd, n, counter, P); break;
-    case 4: hipLaunchKernelGGL((lofk::lof_flag_kernel<false, 48>), grid, blk, 0, st, dd, n, counter, P); break;
-    default: hipLaunchKernelGGL((lofk::lof_flag_kernel<false, 64>), grid, blk, 0, st, dd, n, counter, P); break;
+const void* kernel_of(int k) {
+  switch (k) {
+    case K_STATS: return (const void*)lofk::lof_stats_kernel<true>;
+    case K_STATS + 1: return (const void*)lofk::lof_stats_kernel<false>;
+    case K_TIME + 0: return (const void*)lofk::lof_time_kernel<true, 32>;
+    case K_TIME + 1: return (const void*)lofk::lof_time_kernel<true, 48>;
+    case K_TIME + 2: return (const void*)lofk::lof_time_kernel<true, 64>;
+    case K_TIME + 3: return (const void*)lofk::lof_time_kernel<false, 32>;
+    case K_TIME + 4: return (const void*)lofk::lof_time_kernel<false, 48>;
+    case K_TIME + 5: return (const void*)lofk::lof_time_kernel<false, 64>;
+    case K_FREQ: return (const void*)lofk::lof_freq_kernel<true>;
+    case K_FREQ + 1: return (const void*)lofk::lof_freq_kernel<false>;
+    case K_SIRT + 0: return (const void*)lofk::lof_sir_time_kernel<32>;
+    case K_SIRT + 1: return (const void*)lofk::lof_sir_time_kernel<48>;
+    case K_SIRT + 2: return (const void*)lofk::lof_sir_time_kernel<64>;
+    case K_SIRF: return (const void*)lofk::lof_sir_freq_kernel;
+    case K_FINAL: return (const void*)lofk::lof_final_kernel<true>;
+    default: return (const void*)lofk::lof_final_kernel<false>;
   }
 }
 
@@ -175,6 +184,7 @@ void free_slot(Slot& s) {
   if (s.d_desc) (void)hipFree(s.d_desc);
   if (s.h_desc) (void)hipHostFree(s.h_desc);
   if (s.d_mask) (void)hipFree(s.d_mask);
+  if (s.d_state) (void)hipFree(s.d_state);
   if (s.d_counter) (void)hipFree(s.d_counter);
   if (s.ev) (void)hipEventDestroy(s.ev);
   s = Slot();
@@ -184,7 +194,8 @@ bool alloc_slot(Slot& s, int max_blocks, size_t mask_words) {
   return hipMalloc(&s.d_desc, sizeof(DevBlock) * max_blocks) == hipSuccess &&
          hipHostMalloc(&s.h_desc, sizeof(DevBlock) * max_blocks, hipHostMallocDefault) == hipSuccess &&
          hipMalloc(&s.d_mask, sizeof(uint64_t) * mask_words) == hipSuccess &&
-         hipMalloc(&s.d_counter, sizeof(int) * NVAR) == hipSuccess &&
+         hipMalloc(&s.d_state, sizeof(BlockState) * max_blocks) == hipSuccess &&
+         hipMalloc(&s.d_counter, sizeof(int) * NCOUNTER) == hipSuccess &&
          hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) == hipSuccess;
 }
 
@@ -282,29 +293,79 @@ void build_table(lof_ctx* c, const lof_tuning& t, const lof_block* blocks, int32
     const size_t es = elem_size(b.dtype);
     d.aligned = (((uintptr_t)b.data % 16) == 0 && ((size_t)b.data_row_stride * es) % 16 == 0) ? 1 : 0;
     d.faligned = (((uintptr_t)b.flags % 16) == 0 && (b.flag_row_stride % 16) == 0) ? 1 : 0;
-    d.pad = 0;
+    d.sidx = j;
     moff += (int64_t)b.n_channels * ((b.n_times + 63) / 64);
     counts[variant_of(t, b)]++;
   }
 }
 
-// kernels of one call on stream st (descriptors already on the device in s)
+// one kernel launch over nb blocks (maxch > 0: chunked kernel, nb * maxch items)
+void launch(lof_ctx* c, const lof_tuning& t, int kid, const DevBlock* dd, int nb, int maxch, Slot& s, int& ncounter,
+            hipStream_t st, const DevParams& P) {
+  const int items = maxch > 0 ? nb * maxch : nb;
+  if (items <= 0) return;
+  int* counter = nullptr;
+  int grid = items;
+  if (t.persistent && ncounter < NCOUNTER) {
+    counter = s.d_counter + ncounter++;
+    grid = std::min(items, std::max(1, c->occ[kid]) * std::max(1, c->n_cu));
+  }
+  const DevBlock* a_blocks = dd;
+  int a_nb = nb, a_maxch = maxch;
+  int* a_counter = counter;
+  DevParams a_p = P;
+  if (maxch > 0) {
+    void* args[] = {&a_blocks, &a_nb, &a_maxch, &a_counter, &a_p};
+    (void)hipLaunchKernel(kernel_of(kid), dim3(grid), dim3(lofk::WG), args, 0, st);
+  } else {
+    void* args[] = {&a_blocks, &a_nb, &a_counter, &a_p};
+    (void)hipLaunchKernel(kernel_of(kid), dim3(grid), dim3(lofk::WG), args, 0, st);
+  }
+}
+
+template <class F>
+int max_chunks(const DevBlock* h, int n, F&& f) {
+  int m = 0;
+  for (int i = 0; i < n; ++i) m = std::max(m, f(h[i]));
+  return m;
+}
+
+// kernels of one call on stream st (descriptors already on the device in s and
+// still in s.h_desc, which sizes the chunked launches)
 void enqueue(lof_ctx* c, const lof_tuning& t, Slot& s, const int* counts, int n, void* stats, hipStream_t st,
              bool autocommit) {
-  const DevParams P = dev_params(c, s.d_mask, stats);
-  if (t.persistent) hipLaunchKernelGGL(lofk::lof_zero_kernel, dim3(1), dim3(64), 0, st, s.d_counter, NVAR);
+  const DevParams P = dev_params(c, s.d_mask, s.d_state, stats);
+  if (t.persistent) hipLaunchKernelGGL(lofk::lof_zero_kernel, dim3(1), dim3(64), 0, st, s.d_counter, NCOUNTER);
+  int nc = 0;
   int off = 0;
-  for (int v = 0; v < NVAR; ++v) {
-    const int cnt = counts[v];
-    if (!cnt) continue;
-    const DevBlock* dd = s.d_desc + off;
-    if (t.persistent) {
-      const int cap = std::max(1, c->occ[v]) * std::max(1, c->n_cu);
-      launch_variant(v, dim3(std::min(cnt, cap)), st, dd, cnt, s.d_counter + v, P);
-    } else {
-      launch_variant(v, dim3(cnt), st, dd, cnt, nullptr, P);
+  for (int kind = 0; kind < 2; ++kind) {
+    const int kcnt = counts[3 * kind] + counts[3 * kind + 1] + counts[3 * kind + 2];
+    if (!kcnt) continue;
+    const bool integer = kind == 0;
+    const DevBlock* dk = s.d_desc + off;
+    const DevBlock* hk = s.h_desc + off;
+    launch(c, t, K_STATS + kind, dk, kcnt, 0, s, nc, st, P);
+    int mt[3] = {0, 0, 0};
+    for (int j = 0, voff = 0; j < 3; voff += counts[3 * kind + j], ++j) {
+      const int cnt = counts[3 * kind + j];
+      if (!cnt) continue;
+      const int L = variant_lanes(j);
+      mt[j] = max_chunks(hk + voff, cnt, [&](const DevBlock& b) { return lofk::time_chunks(b.C, b.T, L); });
+      launch(c, t, K_TIME + 3 * kind + j, dk + voff, cnt, mt[j], s, nc, st, P);
     }
-    off += cnt;
+    const int mf = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::freq_chunks(integer, b.C, b.T); });
+    launch(c, t, K_FREQ + kind, dk, kcnt, mf, s, nc, st, P);
+    if (c->prm.sir_eta_num > 0) {
+      for (int j = 0, voff = 0; j < 3; voff += counts[3 * kind + j], ++j) {
+        const int cnt = counts[3 * kind + j];
+        if (cnt) launch(c, t, K_SIRT + j, dk + voff, cnt, mt[j], s, nc, st, P);
+      }
+      const int ms = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::sirf_chunks(b.C, b.T); });
+      launch(c, t, K_SIRF, dk, kcnt, ms, s, nc, st, P);
+    }
+    const int mw = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::final_chunks(b.C); });
+    launch(c, t, K_FINAL + kind, dk, kcnt, mw, s, nc, st, P);
+    off += kcnt;
   }
   if (autocommit) hipLaunchKernelGGL(lofk::lof_commit_desc_kernel, dim3(n), dim3(256), 0, st, s.d_desc, n, P);
 }
@@ -400,8 +461,8 @@ lof_status lof_create(const lof_params* params, int hip_device, lof_ctx** out) {
     hipDeviceProp_t prop;
     ok = hipGetDeviceProperties(&prop, hip_device) == hipSuccess;
     c->n_cu = ok ? prop.multiProcessorCount : 0;
-    for (int v = 0; ok && v < NVAR; ++v)
-      ok = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c->occ[v], kernel_of(v), lofk::WG, 0) == hipSuccess;
+    for (int k = 0; ok && k < NKERN; ++k)
+      ok = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c->occ[k], kernel_of(k), lofk::WG, 0) == hipSuccess;
   }
   if (ok) ok = hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
@@ -587,7 +648,7 @@ lof_status lof_history_update(lof_ctx* c, const int32_t* ids, int32_t n, void* h
   }
   DevGuard g(c->dev);
   hipStream_t st = (hipStream_t)hip_stream;
-  const DevParams P = dev_params(c, nullptr, nullptr);
+  const DevParams P = dev_params(c, nullptr, nullptr, nullptr);
   const int TPB = 256;
   if (!ids) {
     lofk::IdList none;

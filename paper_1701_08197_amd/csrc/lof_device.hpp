@@ -1,20 +1,24 @@
-// lof_device.hpp -- device-side building blocks of the LOF flagging kernel (gfx950).
+// lof_device.hpp -- device-side building blocks of the LOF flagging kernels (gfx950).
 //
 // Method: van Nieuwpoort, "Towards exascale real-time RFI mitigation" (arXiv
-// 1701.08197).  The kernel runs one workgroup per time-frequency block:
-//   phase A  power (Sec. 4), block moments and an exact radix-select median
-//            (Sec. 2.1 threshold, Sec. 4.2 O(N) median), thresholds (Sec. 2.1)
-//   phase B  SumThreshold along time, then along frequency (Sec. 2.1)
-//   phase C  SIR operator along time, then frequency (Sec. 2.2)
-//   phase D  history flagger (Sec. 4.1) and the flag-byte write.
+// 1701.08197).  One kernel per phase, each over (block, chunk) work items:
+//   phase A  power (Sec. 4), block moments and an exact median (Sec. 2.1
+//            threshold, Sec. 4.2 O(N) median), thresholds (Sec. 2.1); per block
+//   phase B  SumThreshold along time (row chunks), then along frequency (column
+//            slabs) (Sec. 2.1)
+//   phase C  SIR operator along time (row chunks), then frequency (slabs) (Sec. 2.2)
+//   phase D  history flagger (Sec. 4.1) and the flag-byte write (row chunks).
+// The phases hand over a per-block statistics record and the mask bits in a
+// global scratch area (one u64 word per 64 samples of a row).
 //
 // Layouts.  A "row" (one channel of the block, along time) is held by a group of
 // G consecutive lanes of a wave64, each lane owning L consecutive samples; a
 // "column" (one time sample, along frequency) is held the same way with channels
-// as positions.  Window sums for I = 2^k are built by doubling,
-// S_2I(s) = S_I(s) + S_I(s + I), which needs at most the neighbouring lane's
-// registers (I/2 <= L), fetched with DPP wave shifts.  Masks are per-lane u64 bit
-// vectors (bit i <-> position lane_in_group*L + i).
+// as positions.  Integer rows keep inclusive prefix sums of the packed samples,
+// so a window is one difference of two prefixes, the far one read from the next
+// lane(s) by DPP wave shifts; float rows and columns build window sums by
+// doubling, S_2I(s) = S_I(s) + S_I(s + I).  Masks are per-lane u64 bit vectors
+// (bit i <-> position lane_in_group*L + i).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -56,8 +60,53 @@ struct DevBlock {
   int32_t out_idx;      // index of the caller's stats entry
   int32_t aligned;      // data rows 16-byte aligned
   int32_t faligned;     // flag rows 16-byte aligned
-  int32_t pad;
+  int32_t sidx;         // index of the block's BlockState in this call
 };
+
+// Per-block results of the statistics kernel, read by the later kernels.
+struct BlockState {
+  double median, sigma;
+  double T[16];          // T_k of level k (window 2^k)
+};
+
+// ---------------------------------------------------------------- work split
+// Each kernel after the statistics one takes a block in chunks: rows for the
+// time-direction kernels, column slabs for the frequency-direction kernels.  The
+// host sizes the grid with the same functions.
+__host__ __device__ inline int time_groups(int T, int L) {   // lanes per row (T <= 64 L)
+  int G = 1;
+  while (G * L < T) G <<= 1;
+  return G;
+}
+__host__ __device__ inline int time_rows_per_chunk(int T, int L) {
+  return T <= 64 * L ? NW * (64 / time_groups(T, L)) : NW;
+}
+__host__ __device__ inline int time_chunks(int C, int T, int L) {
+  const int r = time_rows_per_chunk(T, L);
+  return (C + r - 1) / r;
+}
+__host__ __device__ inline bool freq_colpath(bool integer, int C) {
+  return integer && (C == 16 || C == 32 || C == 64);
+}
+// columns of one frequency slab: LF channels per lane, G lanes per column
+__host__ __device__ inline int freq_cols(int C, int LF_min16) {
+  const int LF = (C <= 16 && LF_min16) ? 16 : 32;
+  int G = 1;
+  while (G * LF < C) G <<= 1;
+  return NW * (64 / G);
+}
+// a chunk covers whole 64-column mask words, so no two workgroups share a word
+__host__ __device__ inline int freq_span(bool integer, int C) {
+  if (freq_colpath(integer, C)) return NW * 64;
+  const int cols = freq_cols(C, 1);
+  return cols < 64 ? 64 : cols;
+}
+__host__ __device__ inline int freq_chunks(bool integer, int C, int T) {
+  const int span = freq_span(integer, C);
+  return (T + span - 1) / span;
+}
+__host__ __device__ inline int sirf_chunks(int C, int T) { return freq_chunks(false, C, T); }
+__host__ __device__ inline int final_chunks(int C) { return (C + NW - 1) / NW; }
 
 struct DevParams {
   double start, p, sens, hs;
@@ -68,6 +117,7 @@ struct DevParams {
   double* pend;          // [streams][maxC]
   uint8_t* pvalid;       // [streams][maxC]
   uint64_t* maskw;       // mask scratch of this call
+  BlockState* bstate;    // per-block statistics of this call
   void* stats;           // lof_block_stats* or null
 };
 
@@ -234,35 +284,71 @@ constexpr int TILE_ELEMS = NW * 64 * 32;   // frequency slab: (G*32 channels) x 
 constexpr int TILE_PAD = 1024;             // one padding element per slab row (<= 1024 rows)
 constexpr int TILE_WORDS = 1024;           // mask words of one frequency slab
 
+// Shared memory of each kernel: only what that kernel's phase uses.
 template <bool INT>
-struct SmemT {
-  typedef typename TileOf<INT>::T TileT;
-  // integer slabs hold 64 columns per wave (one lane per column, up to 64
-  // channels): 64 x 513 u16; float slabs the generic (G*32) x (NW*64/G + 1)
-  static constexpr int TE = INT ? (64 * (NW * 64 + 1)) : (TILE_ELEMS + TILE_PAD);
+struct SmStats {
   union {
-    uint32_t ihist[INT ? IHIST_WORDS : 1];   // phase A, integer input: full-resolution histogram
-    uint32_t hist[2][HBINS];                 // phase A: 12-bit digit histograms (radix select)
-    struct {
-      TileT t[TE];                           // frequency slab of powers (u16 values / float)
-      uint64_t w[TILE_WORDS];                // mask words of the slab
-    } f;
-    struct {
-      double rsum[MAXC];                     // history: per-row unflagged sum
-      int32_t rcnt[MAXC];                    // history: per-row unflagged count
-      int32_t seg[NW][SIR_MAX_SEGS][3];      // SIR: per-segment summaries / carries
-    } c;
+    uint32_t ihist[INT ? IHIST_WORDS : 1];   // integer input: full-resolution histogram
+    uint32_t hist[2][HBINS];                 // 12-bit digit histograms (radix select)
   } u;
   double T[16];
   float Tf[16];
-  int32_t G[ST_MAX_LEVELS][128];   // index: window count c (<= 64); padded to any 7-bit value
-  uint32_t rowflag[MAXC / 32];
   double red_d[2][NW];
   unsigned long long red_u[2][NW];
   uint32_t scan[NW];
   uint32_t sel[4];
   double median, sigma;
-  unsigned long long nflag;
+};
+
+// thresholds of the block as the SumThreshold passes use them
+struct SmThr {
+  double T[16];
+  float Tf[16];
+  int32_t G[ST_MAX_LEVELS][128];   // index: window count c (<= 64); padded to any 7-bit value
+};
+
+template <bool INT>
+struct SmFreq {
+  typedef typename TileOf<INT>::T TileT;
+  // integer slabs hold 64 columns per wave (one lane per column, up to 64
+  // channels): 64 x 513 u16; float slabs the generic (G*32) x (NW*64/G + 1)
+  static constexpr int TE = INT ? (64 * (NW * 64 + 1)) : (TILE_ELEMS + TILE_PAD);
+  union {
+    struct {
+      TileT t[TE];                 // frequency slab of powers (u16 values / float)
+      uint64_t w[TILE_WORDS];      // mask words of the slab
+    } f;
+  } u;
+  double T[16];
+  float Tf[16];
+  int32_t G[ST_MAX_LEVELS][128];
+};
+
+struct SmSirT {
+  union {
+    struct {
+      int32_t seg[NW][SIR_MAX_SEGS][3];   // per-segment summaries / carries of long rows
+    } c;
+  } u;
+};
+
+struct SmSirF {
+  union {
+    struct {
+      uint64_t w[TILE_WORDS];
+    } f;
+  } u;
+};
+
+struct SmFinal {
+  union {
+    struct {
+      double rsum[MAXC];          // per-row unflagged sum
+      int32_t rcnt[MAXC];         // per-row unflagged count
+    } c;
+  } u;
+  uint32_t rowflag[MAXC / 32];
+  unsigned long long red_u[2][NW];
 };
 
 }  // namespace lofk

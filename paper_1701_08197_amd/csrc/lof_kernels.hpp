@@ -335,9 +335,22 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
     }
   }
   __syncthreads();
+}
+
+// Thresholds of a block from its BlockState into shared memory.  Integer input
+// also gets exact window thresholds: flag iff S > floor(c * T_k), stored packed
+// against the window word D = S*512 + 4c as G = floor(c*T_k)*512 + 511.
+template <bool INT, class SM>
+__device__ __forceinline__ void load_thresholds(const DevBlock& b, const DevParams& P, SM& sm) {
+  const int tid = threadIdx.x;
+  const GLB BlockState* bs = gp<const BlockState>(P.bstate) + b.sidx;
+  if (tid < 16) {
+    const double t = bs->T[tid];
+    sm.T[tid] = t;
+    sm.Tf[tid] = (float)t;
+  }
+  __syncthreads();
   if (INT) {
-    // exact integer window thresholds: flag iff S > floor(c * T_k); stored packed
-    // against the window word D = S*512 + 4c as G = floor(c*T_k)*512 + 511.
     for (int i = tid; i < ST_MAX_LEVELS * 128; i += WG) {
       const int k = i >> 7, c = i & 127;
       const double T = sm.T[k];
@@ -352,8 +365,8 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
       else g = (int32_t)fl * 512 + 511;
       sm.G[k][c] = g;
     }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // ===================================================================== SumThreshold core
@@ -523,6 +536,155 @@ __device__ __forceinline__ uint64_t st_core(LD& ld, uint64_t fm, const int lig, 
   return fm;
 }
 
+// Integer input, prefix form.  A lane keeps the inclusive prefix sums
+// Y[i] = sum of v over the group's positions up to lig*L + i, modulo 2^32: every
+// true window word is below 2^30, so differences of prefixes are exact.  The
+// window of I starting at lane position i is Y(i+I-1) - Y(i-1); Y(j) for j >= L
+// comes from the next one or two lanes by DPP, Y(-1) is the prefix before the
+// lane (0 in the first lane of a group).  A level that changed the mask refills
+// v and recomputes the prefixes once, at a cost that does not grow with the level.
+template <int L>
+__device__ __forceinline__ uint32_t px_get(const uint32_t (&Y)[L], int j) {
+  if (j < L) return Y[j < L ? j : 0];
+  if (j < 2 * L) return shl1(Y[(j >= L && j < 2 * L) ? j - L : 0]);
+  return shl1(shl1(Y[(j >= 2 * L && j < 3 * L) ? j - 2 * L : 0]));
+}
+
+template <int L>
+__device__ __forceinline__ uint32_t px_win(const uint32_t (&Y)[L], uint32_t yprev, int i, int I) {
+  const uint32_t lo = (i == 0) ? yprev : Y[(i > 0) ? i - 1 : 0];
+  return px_get<L>(Y, i + I - 1) - lo;
+}
+
+// v under mask fm -> prefixes; returns Y(-1)
+template <int L, class LD>
+__device__ __forceinline__ uint32_t px_fill(LD& ld, uint64_t fm, uint32_t (&Y)[L], int lig, int G) {
+  float unused[L];
+  ld.fill(fm, Y, unused);
+  uint32_t run = 0;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    run += Y[i];
+    Y[i] = run;
+  }
+  uint32_t incl = run;
+  for (int d = 1; d < G; d <<= 1) {
+    const uint32_t y = __shfl_up(incl, d, G);
+    if (lig >= d) incl += y;
+  }
+  const uint32_t off = incl - run;
+#pragma unroll
+  for (int i = 0; i < L; ++i) Y[i] += off;
+  return off;
+}
+
+// Remove the samples of `drop` (newly flagged positions of the lane) from the
+// prefixes: a sample's packed value is Y[i] - Y[i-1], and every later prefix of
+// the group loses the sum of dropped values before it.
+template <int L>
+__device__ __forceinline__ void px_drop(uint32_t (&Y)[L], uint32_t& yprev, uint64_t drop, int lig, int G) {
+  const uint32_t dlo = (uint32_t)drop, dhi = (uint32_t)(drop >> 32);
+  uint32_t run = 0, prev = yprev;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const uint32_t y = Y[i];
+    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)(i < 32 ? dlo : dhi), i & 31, 1);   // 0 or ~0
+    run += (y - prev) & m;
+    prev = y;
+    Y[i] = y - run;
+  }
+  uint32_t incl = run;
+  for (int d = 1; d < G; d <<= 1) {
+    const uint32_t t = __shfl_up(incl, d, G);
+    if (lig >= d) incl += t;
+  }
+  const uint32_t off = incl - run;
+#pragma unroll
+  for (int i = 0; i < L; ++i) Y[i] -= off;
+  yprev -= off;
+}
+
+// Window bits are assembled most significant first: acc = (acc << 1) | sign(g - d),
+// one v_alignbit per window.  For every full window d <= 2^30 and
+// -2^30 < g < 2^31, so g - d does not overflow and its sign is (d > g).
+// The empty asm pins d: without it the compiler folds g into the window
+// difference, (g + Y[i-1]) - dpp(Y[j]), and that combined DPP subtract gave
+// wrong lane-crossing windows on gfx950 while the plain form, dpp(Y[j]) - Y[i-1],
+// is exact.
+__device__ __forceinline__ uint32_t push_bit(uint32_t acc, int32_t g, uint32_t d) {
+  asm("" : "+v"(d));
+  return __builtin_amdgcn_alignbit(acc, (uint32_t)(g - (int32_t)d), 31);
+}
+
+template <int L, int K, class SM>
+__device__ __forceinline__ void st_level_px(uint32_t (&Y)[L], uint32_t& yprev, uint64_t& fm, uint64_t& pend,
+                                            const int lig, const int G, const int n, const int pos0,
+                                            const uint64_t vmask, const SM& sm) {
+  constexpr int I = 1 << K;
+  static_assert(I <= 2 * L && L % 16 == 0, "a window may reach at most two lanes ahead");
+  if (__ballot(pend != 0) != 0) px_drop<L>(Y, yprev, pend, lig, G);
+  pend = 0;
+  const int nvw = n - I + 1 - pos0;
+  const int32_t* Gk = sm.G[K];
+  uint32_t lo = 0, hi = 0;
+  if (__ballot(fm != 0) == 0) {
+    // nothing flagged in the wave: every full window counts I samples
+    const int32_t g = Gk[I];
+#pragma unroll
+    for (int i = L - 1; i >= 0; --i) {
+      const uint32_t d = px_win<L>(Y, yprev, i, I);
+      if (i >= 32) hi = push_bit(hi, g, d); else lo = push_bit(lo, g, d);
+    }
+  } else {
+    // sixteen windows at a time: all table reads in flight before they are used
+#pragma unroll
+    for (int i0 = L - 16; i0 >= 0; i0 -= 16) {
+      uint32_t d[16];
+      int32_t g[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        d[j] = px_win<L>(Y, yprev, i0 + j, I);
+        g[j] = Gk[(d[j] >> 2) & 127u];
+      }
+#pragma unroll
+      for (int j = 15; j >= 0; --j) {
+        if (i0 + j >= 32) hi = push_bit(hi, g[j], d[j]); else lo = push_bit(lo, g[j], d[j]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  uint64_t wf = (uint64_t)lo | ((uint64_t)hi << 32);
+  wf &= lowmask(nvw) & vmask;
+  if (__ballot(wf != 0) == 0) return;
+  const uint64_t nb = spread<L, I>(wf, lig) & vmask;
+  pend = nb & ~fm;
+  fm |= nb;
+}
+
+template <int L, class LD, class SM>
+__device__ __forceinline__ uint64_t st_core_px(LD& ld, uint64_t fm, const int lig, const int G, const int n,
+                                               const int nlev, const SM& sm) {
+  uint32_t Y[L];
+  const int pos0 = lig * L;
+  const int nval = clampi(n - pos0, 0, L);
+  const uint64_t vmask = lowmask(nval);
+  int kend = 0;
+  while (kend < nlev && (1 << kend) <= n) ++kend;   // levels with I <= n
+  uint32_t yprev = px_fill<L>(ld, fm, Y, lig, G);
+  uint64_t pend = 0;
+#define LOF_PLEVEL(K) \
+  if (K < kend) st_level_px<L, K>(Y, yprev, fm, pend, lig, G, n, pos0, vmask, sm);
+  LOF_PLEVEL(0)
+  LOF_PLEVEL(1)
+  LOF_PLEVEL(2)
+  LOF_PLEVEL(3)
+  LOF_PLEVEL(4)
+  LOF_PLEVEL(5)
+  LOF_PLEVEL(6)
+#undef LOF_PLEVEL
+  return fm;
+}
+
 // ---- loaders
 struct RowSrc {        // the descriptor fields a row loader needs, by value
   const void* data;
@@ -668,7 +830,7 @@ __device__ __forceinline__ void or_bit_lds(uint64_t* w, int idx, int bit) {
 
 // ===================================================================== phase B
 template <bool INT, int L, class SM>
-__device__ __forceinline__ void phase_time(const DevBlock& b, const DevParams& P, SM& sm) {
+__device__ __forceinline__ void phase_time(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int T = b.T, C = b.C;
   const int W = (T + 63) >> 6;
@@ -678,22 +840,27 @@ __device__ __forceinline__ void phase_time(const DevBlock& b, const DevParams& P
     int G = 1;
     while (G * L < T) G <<= 1;
     const int R = 64 / G, lig = lane & (G - 1), grp = lane / G;
-    for (int rb = wv * R; rb < C; rb += NW * R) {
+    const int rend = (chunk + 1) * NW * R;
+    for (int rb = chunk * NW * R + wv * R; rb < C && rb < rend; rb += NW * R) {
       const int row = rb + grp;
       const bool ok = row < C;
       TimeLoader<INT, L> ld{RowSrc(b), ok ? row : 0, lig * L, clampi(T - lig * L, 0, L), ok};
-      const uint64_t fm = st_core<INT, L>(ld, 0ull, lig, T, 0, nlev, sm);
+      uint64_t fm;
+      if constexpr (INT) fm = st_core_px<L>(ld, 0ull, lig, G, T, nlev, sm);
+      else fm = st_core<INT, L>(ld, 0ull, lig, T, 0, nlev, sm);
       write_row_bits<L>(m0 + (int64_t)(ok ? row : 0) * W, W, fm, lig, G, ok);
     }
   } else {
     // long rows: segments of 64*L positions, SEG_CORE finished positions each
-    for (int row = wv; row < C; row += NW) {
+    for (int row = chunk * NW + wv; row < C && row < (chunk + 1) * NW; row += NW) {
       for (int c0 = 0; c0 < T; c0 += SEG_CORE) {
         const int c1 = min(T, c0 + SEG_CORE);
         const int q0 = max(0, c0 - SEG_HALO);
         const int n = min(T, q0 + 64 * L) - q0;
         TimeLoader<INT, L> ld{RowSrc(b), row, q0 + lane * L, clampi(n - lane * L, 0, L), true};
-        const uint64_t fm = st_core<INT, L>(ld, 0ull, lane, n, 0, nlev, sm);
+        uint64_t fm;
+        if constexpr (INT) fm = st_core_px<L>(ld, 0ull, lane, 64, n, nlev, sm);
+        else fm = st_core<INT, L>(ld, 0ull, lane, n, 0, nlev, sm);
         const int pos = q0 + lane * L;   // L == 64: one word per lane
         if (L == 64 && pos >= c0 && pos < c1) m0[(int64_t)row * W + (pos >> 6)] = fm;
       }
@@ -721,9 +888,9 @@ struct FreqShape {
   }
 };
 
-template <bool INT, class SM>
+template <bool INT, bool POWERS, class SM>
 __device__ __forceinline__ void stage_slab(const DevBlock& b, SM& sm, const GLB uint64_t* m0, int W, int it0, int ncols, int wb,
-                           int nwl, int stride, bool powers) {
+                           int nwl, int stride) {
   typedef typename PowT<INT>::T VT;
   const int tid = threadIdx.x, C = b.C;
   const FastDiv fw((uint32_t)nwl);
@@ -731,7 +898,7 @@ __device__ __forceinline__ void stage_slab(const DevBlock& b, SM& sm, const GLB 
     const int c = (int)fw.div((uint32_t)i), j = i - c * nwl;
     sm.u.f.w[i] = m0[(int64_t)c * W + wb + j];
   }
-  if (powers) {
+  if constexpr (POWERS) {
     const int nch8 = (ncols + 7) >> 3;
     const FastDiv f8((uint32_t)nch8);
     for (int i = tid; i < C * nch8; i += WG) {
@@ -746,18 +913,19 @@ __device__ __forceinline__ void stage_slab(const DevBlock& b, SM& sm, const GLB 
 }
 
 template <bool INT, int LF, class SM>
-__device__ __forceinline__ void phase_freq_l(const DevBlock& b, const DevParams& P, SM& sm) {
+__device__ __forceinline__ void phase_freq_l(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
   const int T = b.T, C = b.C;
   const int W = (T + 63) >> 6;
   GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
   const int nlev = min(P.nl_f, ST_MAX_LEVELS);
   const FreqShape fs(C, lane);
-  for (int it0 = 0; it0 < T; it0 += fs.cpi) {
+  const int span = max(fs.cpi, 64);
+  for (int it0 = chunk * span; it0 < T && it0 < (chunk + 1) * span; it0 += fs.cpi) {
     const int ncols = min(fs.cpi, T - it0);
     const int wb = it0 >> 6;
     const int nwl = ((it0 + ncols - 1) >> 6) - wb + 1;
-    stage_slab<INT>(b, sm, m0, W, it0, ncols, wb, nwl, fs.stride, true);
+    stage_slab<INT, true>(b, sm, m0, W, it0, ncols, wb, nwl, fs.stride);
     __syncthreads();
     const int col = wv * fs.cpw + fs.colw;
     const int t = it0 + col;
@@ -824,23 +992,29 @@ __device__ __forceinline__ void col_level(const uint16_t* tile, int stride, int 
 #pragma unroll
     for (int i = 0; i + I <= NC; ++i) D[i] += D[i + I / 2];
     const int32_t* Gk = sm.G[K];
-    unsigned long long any = 0;
+    constexpr int NWIN = NC - I + 1;   // full windows of the column
+    uint32_t lo = 0, hi = 0;
 #pragma unroll
-    for (int i = 0; i + I <= NC; ++i) {
-      any |= __ballot((int32_t)D[i] > Gk[(D[i] >> 2) & 127u]);
-      if ((i & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+    for (int i0 = ((NWIN - 1) / 16) * 16; i0 >= 0; i0 -= 16) {
+      int32_t g[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (i0 + j < NWIN) g[j] = Gk[(D[i0 + j < NWIN ? i0 + j : 0] >> 2) & 127u];
+#pragma unroll
+      for (int j = 15; j >= 0; --j) {
+        if (i0 + j < NWIN) {
+          const uint32_t d = D[i0 + j < NWIN ? i0 + j : 0];
+          if (i0 + j >= 32) hi = push_bit(hi, g[j], d); else lo = push_bit(lo, g[j], d);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
-    if (any == 0) {
+    uint64_t wf = (uint64_t)lo | ((uint64_t)hi << 32);
+    if (!ok) wf = 0;
+    if (__ballot(wf != 0) == 0) {
       dirty = false;
       return;
     }
-    uint64_t wf = 0;
-#pragma unroll
-    for (int i = 0; i + I <= NC; ++i) {
-      wf |= (uint64_t)(((int32_t)D[i] > Gk[(D[i] >> 2) & 127u]) ? 1u : 0u) << i;
-      if ((i & 15) == 15) __builtin_amdgcn_sched_barrier(0);
-    }
-    if (!ok) wf = 0;
     uint64_t nb = wf;
 #pragma unroll
     for (int d = 1; d < I; d <<= 1) nb |= nb << d;
@@ -869,18 +1043,18 @@ __device__ __forceinline__ uint64_t st_col(const uint16_t* tile, int stride, int
 }
 
 template <int NC, class SM>
-__device__ __forceinline__ void phase_freq_col(const DevBlock& b, const DevParams& P, SM& sm) {
+__device__ __forceinline__ void phase_freq_col(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
   const int T = b.T, C = NC;
   const int W = (T + 63) >> 6;
   GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
   const int nlev = min(P.nl_f, ST_MAX_LEVELS);
   constexpr int cpi = NW * 64, stride = cpi + 1;
-  for (int it0 = 0; it0 < T; it0 += cpi) {
+  for (int it0 = chunk * cpi; it0 < T && it0 < (chunk + 1) * cpi; it0 += cpi) {
     const int ncols = min(cpi, T - it0);
     const int wb = it0 >> 6;
     const int nwl = ((it0 + ncols - 1) >> 6) - wb + 1;
-    stage_slab<true>(b, sm, m0, W, it0, ncols, wb, nwl, stride, true);
+    stage_slab<true, true>(b, sm, m0, W, it0, ncols, wb, nwl, stride);
     __syncthreads();
     const int col = wv * 64 + lane;
     const bool ok = col < ncols;
@@ -911,16 +1085,16 @@ __device__ __forceinline__ void phase_freq_col(const DevBlock& b, const DevParam
 }
 
 template <bool INT, class SM>
-__device__ __forceinline__ void phase_freq(const DevBlock& b, const DevParams& P, SM& sm) {
+__device__ __forceinline__ void phase_freq(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
   const int C = b.C;
   if (C <= 1 || P.nl_f <= 1) return;
   if constexpr (INT) {
-    if (C == 64) return phase_freq_col<64>(b, P, sm);
-    if (C == 32) return phase_freq_col<32>(b, P, sm);
-    if (C == 16) return phase_freq_col<16>(b, P, sm);
+    if (C == 64) return phase_freq_col<64>(b, P, sm, chunk);
+    if (C == 32) return phase_freq_col<32>(b, P, sm, chunk);
+    if (C == 16) return phase_freq_col<16>(b, P, sm, chunk);
   }
-  if (C <= 16) phase_freq_l<INT, 16>(b, P, sm);
-  else phase_freq_l<INT, 32>(b, P, sm);
+  if (C <= 16) phase_freq_l<INT, 16>(b, P, sm, chunk);
+  else phase_freq_l<INT, 32>(b, P, sm, chunk);
 }
 
 // ===================================================================== phase C: SIR
@@ -1004,7 +1178,7 @@ __device__ __forceinline__ uint64_t sir_lane_apply(uint64_t bits, int nval, int 
 }
 
 template <int L, class SM>
-__device__ __forceinline__ void phase_sir_time(const DevBlock& b, const DevParams& P, SM& sm) {
+__device__ __forceinline__ void phase_sir_time(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int T = b.T, C = b.C;
   const int W = (T + 63) >> 6;
@@ -1014,7 +1188,8 @@ __device__ __forceinline__ void phase_sir_time(const DevBlock& b, const DevParam
     int G = 1;
     while (G * L < T) G <<= 1;
     const int R = 64 / G, lig = lane & (G - 1), grp = lane / G;
-    for (int rb = wv * R; rb < C; rb += NW * R) {
+    const int rend = (chunk + 1) * NW * R;
+    for (int rb = chunk * NW * R + wv * R; rb < C && rb < rend; rb += NW * R) {
       const int row = rb + grp;
       const bool ok = row < C;
       GLB uint64_t* rp = m0 + (int64_t)(ok ? row : 0) * W;
@@ -1032,7 +1207,7 @@ __device__ __forceinline__ void phase_sir_time(const DevBlock& b, const DevParam
     // long rows (L == 64): SIR_SEG positions per segment, two passes with carries
     const int nseg = (T + SIR_SEG - 1) / SIR_SEG;
     int(*seg)[3] = sm.u.c.seg[wv];
-    for (int row = wv; row < C; row += NW) {
+    for (int row = chunk * NW + wv; row < C && row < (chunk + 1) * NW; row += NW) {
       GLB uint64_t* rp = m0 + (int64_t)row * W;
       bool any = false;
       for (int s = 0; s < nseg; ++s) {
@@ -1087,18 +1262,19 @@ __device__ __forceinline__ void phase_sir_time(const DevBlock& b, const DevParam
 }
 
 template <int LF, class SM>
-__device__ __forceinline__ void phase_sir_freq_l(const DevBlock& b, const DevParams& P, SM& sm) {
+__device__ __forceinline__ void phase_sir_freq_l(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
   const int T = b.T, C = b.C;
   const int W = (T + 63) >> 6;
   GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
   const int num = P.eta_num, den = P.eta_den;
   const FreqShape fs(C, lane);
-  for (int it0 = 0; it0 < T; it0 += fs.cpi) {
+  const int span = max(fs.cpi, 64);
+  for (int it0 = chunk * span; it0 < T && it0 < (chunk + 1) * span; it0 += fs.cpi) {
     const int ncols = min(fs.cpi, T - it0);
     const int wb = it0 >> 6;
     const int nwl = ((it0 + ncols - 1) >> 6) - wb + 1;
-    stage_slab<true>(b, sm, m0, W, it0, ncols, wb, nwl, fs.stride, false);
+    stage_slab<true, false>(b, sm, m0, W, it0, ncols, wb, nwl, fs.stride);
     __syncthreads();
     const int col = wv * fs.cpw + fs.colw;
     const int t = it0 + col;
@@ -1134,20 +1310,22 @@ __device__ __forceinline__ void phase_sir_freq_l(const DevBlock& b, const DevPar
 }
 
 template <class SM>
-__device__ __forceinline__ void phase_sir_freq(const DevBlock& b, const DevParams& P, SM& sm) {
+__device__ __forceinline__ void phase_sir_freq(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
   const int C = b.C;
   if (C <= 1) return;
-  if (C <= 16) phase_sir_freq_l<16>(b, P, sm);
-  else phase_sir_freq_l<32>(b, P, sm);
+  if (C <= 16) phase_sir_freq_l<16>(b, P, sm, chunk);
+  else phase_sir_freq_l<32>(b, P, sm, chunk);
 }
 
 // ===================================================================== phase D
-// History flagger (Sec. 4.1): per channel, the mean of this block's unflagged
-// samples against mean + history_sensitivity * stddev of the committed means.
+// History flagger (Sec. 4.1) on the rows [r0, r1) of a block: per channel, the
+// mean of this block's unflagged samples against mean + history_sensitivity *
+// stddev of the committed means.
 template <bool INT, class SM>
-__device__ __forceinline__ void phase_history(const DevBlock& b, const DevParams& P, SM& sm) {
+__device__ __forceinline__ void phase_history(const DevBlock& b, const DevParams& P, SM& sm, const int r0,
+                                              const int r1) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int T = b.T, C = b.C;
+  const int T = b.T;
   const int W = (T + 63) >> 6;
   const GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
   for (int i = tid; i < MAXC / 32; i += WG) sm.rowflag[i] = 0u;
@@ -1157,7 +1335,7 @@ __device__ __forceinline__ void phase_history(const DevBlock& b, const DevParams
   }
   typedef typename PowT<INT>::T VT;
   const int nch = (T + 7) >> 3;
-  for (int row = wv; row < C; row += NW) {
+  for (int row = r0 + wv; row < r1; row += NW) {
     unsigned long long su = 0;
     double sd = 0.0;
     int cnt = 0;
@@ -1192,7 +1370,7 @@ __device__ __forceinline__ void phase_history(const DevBlock& b, const DevParams
   }
   __syncthreads();
   const int s = b.stream_id;
-  for (int row = tid; row < C; row += WG) {
+  for (int row = r0 + tid; row < r1; row += WG) {
     const int64_t idx = (int64_t)s * P.maxC + row;
     const int cnt = sm.u.c.rcnt[row];
     if (cnt == 0) {
@@ -1232,20 +1410,23 @@ __device__ __forceinline__ void phase_history(const DevBlock& b, const DevParams
   __syncthreads();
 }
 
-// final flags = SIR mask OR history rows; one byte per sample
+// final flags of the rows [r0, r1) = SIR mask OR history rows; one byte per
+// sample.  The block's flagged-sample and history-row totals are accumulated in
+// the caller's stats entry (zeroed by the statistics kernel).
 template <class SM>
-__device__ __forceinline__ void phase_write(const DevBlock& b, const DevParams& P, SM& sm) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int T = b.T, C = b.C;
+__device__ __forceinline__ void phase_write(const DevBlock& b, const DevParams& P, SM& sm, const int r0, const int r1) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int T = b.T;
   const int W = (T + 63) >> 6;
   const GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
   const int nch = (T + 15) >> 4;
-  const uint32_t items = (uint32_t)C * (uint32_t)nch;
+  const uint32_t items = (uint32_t)(r1 - r0) * (uint32_t)nch;
   const FastDiv fd((uint32_t)nch);
   unsigned long long nfl = 0;
   for (uint32_t it = tid; it < items; it += WG) {
-    const int row = (int)fd.div(it);
-    const int t0 = (int)(it - (uint32_t)row * (uint32_t)nch) * 16;
+    const int rr = (int)fd.div(it);
+    const int row = r0 + rr;
+    const int t0 = (int)(it - (uint32_t)rr * (uint32_t)nch) * 16;
     const uint64_t w = ld_mask(m0 + (int64_t)row * W + (t0 >> 6));
     uint32_t fb = (uint32_t)(w >> (t0 & 63)) & 0xffffu;
     if ((sm.rowflag[row >> 5] >> (row & 31)) & 1u) fb = 0xffffu;
@@ -1265,81 +1446,138 @@ __device__ __forceinline__ void phase_write(const DevBlock& b, const DevParams& 
       for (int j = 0; j < nv; ++j) fp[j] = (uint8_t)((fb >> j) & 1u);
     }
   }
+  if (!P.stats) return;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) nfl += __shfl_xor(nfl, d);
-  if (lane == 0) sm.red_u[0][wv] = nfl;
-  __syncthreads();
-  if (tid == 0 && P.stats) {
-    unsigned long long tot = 0;
-    for (int w = 0; w < NW; ++w) tot += sm.red_u[0][w];
+  char* st = (char*)P.stats + (int64_t)b.out_idx * (int64_t)(18 * 8 + 16);
+  if (lane == 0 && nfl) atomicAdd((unsigned long long*)(st + 18 * 8), nfl);
+  if (tid == 0) {
     int hr = 0;
-    for (int i = 0; i < MAXC / 32; ++i) hr += __builtin_popcount(sm.rowflag[i]);
-    GLB double* st = (GLB double*)(gp<char>(P.stats) + (int64_t)b.out_idx * (int64_t)(18 * 8 + 16));
-    st[0] = sm.median;
-    st[1] = sm.sigma;
-    const int nT = max(P.nl_t, P.nl_f);
-    for (int k = 0; k < 16; ++k) st[2 + k] = k < nT ? sm.T[k] : 0.0;
-    *(GLB long long*)(st + 18) = (long long)tot;
-    *(GLB int*)(st + 19) = hr;
-    *((GLB int*)(st + 19) + 1) = 0;
+    for (int row = r0; row < r1; ++row) hr += (sm.rowflag[row >> 5] >> (row & 31)) & 1u;
+    if (hr) atomicAdd((int*)(st + 19 * 8), hr);
   }
 }
 
 // ===================================================================== kernels
-// Phase boundary: every wave's mask stores must be visible to the other waves of
-// the workgroup.  All waves of a workgroup run on one CU and share its
-// write-through L1, so a workgroup-scope fence plus barrier suffices (a
-// device-scope fence would write back the whole L2).
-__device__ __forceinline__ void phase_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
+// One kernel per phase; a phase's mask stores reach the next kernel through the
+// kernel boundary on the same stream.
 #ifndef LOF_WAVES_PER_EU
 #define LOF_WAVES_PER_EU 4
 #endif
 
-template <bool INT, int L, class SM>
-__device__ __forceinline__ void flag_one_block(const DevBlock& b, const DevParams& P, SM& sm) {
-  phase_stats<INT>(b, P, sm);
-  phase_time<INT, L>(b, P, sm);
-  phase_sync();
-  phase_freq<INT>(b, P, sm);
-  phase_sync();
-  if (P.eta_num > 0) {
-    phase_sir_time<L>(b, P, sm);
-    phase_sync();
-    phase_sir_freq(b, P, sm);
-    phase_sync();
+// A kernel's work items are (block, chunk) pairs, item = block * maxch + chunk;
+// chunks past a smaller block's count return at once.  With counter == nullptr
+// each workgroup takes one item; otherwise a persistent grid takes the next item
+// from a device counter until all are done.
+template <class F>
+__device__ __forceinline__ void run_items(int nitems, int* counter, F&& f) {
+  __shared__ int cur;
+  int it = (int)blockIdx.x;
+  for (;;) {
+    if (counter != nullptr) {
+      if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
+      __syncthreads();
+      it = cur;
+      __syncthreads();
+    }
+    if (it >= nitems) break;
+    f(it);   // the one call site: always inlined
+    if (counter == nullptr) break;
+    __syncthreads();
   }
-  phase_history<INT>(b, P, sm);
-  phase_write(b, P, sm);
 }
 
-// One workgroup per block (counter == nullptr), or a persistent grid whose
-// workgroups take the next block index from a device counter until the table
-// (ordered largest first) is exhausted.
-template <bool INT, int L>
-__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_flag_kernel(const DevBlock* __restrict__ blocks, int nb,
-                                                                        int* counter, DevParams P) {
-  __shared__ SmemT<INT> sm;
-  if (counter == nullptr) {
-    const DevBlock b = blocks[blockIdx.x];
-    flag_one_block<INT, L>(b, P, sm);
-    return;
-  }
-  __shared__ int cur;
-  for (;;) {
-    if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
-    __syncthreads();
-    const int bi = cur;
-    __syncthreads();
-    if (bi >= nb) break;
+// Phase A: power, median, stddev and thresholds of each block -> BlockState and
+// the caller's stats entry (whose flag totals the final kernel accumulates).
+template <bool INT>
+__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_stats_kernel(const DevBlock* __restrict__ blocks, int nb,
+                                                                         int* counter, DevParams P) {
+  __shared__ SmStats<INT> sm;
+  run_items(nb, counter, [&](int bi) __attribute__((always_inline)) {
     const DevBlock b = blocks[bi];
-    flag_one_block<INT, L>(b, P, sm);
-    __syncthreads();
-  }
+    phase_stats<INT>(b, P, sm);
+    const int k = threadIdx.x;
+    if (k < 18) {
+      GLB BlockState* bs = gp<BlockState>(P.bstate) + b.sidx;
+      if (k == 0) bs->median = sm.median;
+      else if (k == 1) bs->sigma = sm.sigma;
+      else bs->T[k - 2] = sm.T[k - 2];
+    }
+    if (P.stats && k < 20) {
+      GLB double* st = (GLB double*)(gp<char>(P.stats) + (int64_t)b.out_idx * (int64_t)(18 * 8 + 16));
+      if (k == 0) st[0] = sm.median;
+      else if (k == 1) st[1] = sm.sigma;
+      else if (k < 18) st[k] = sm.T[k - 2];
+      else *(GLB long long*)(st + k) = 0;   // flagged samples; history rows and padding
+    }
+  });
+}
+
+// Phase B, time direction: rows of a block in chunks
+template <bool INT, int L>
+__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_time_kernel(const DevBlock* __restrict__ blocks, int nb,
+                                                                        int maxch, int* counter, DevParams P) {
+  __shared__ SmThr sm;
+  run_items(nb * maxch, counter, [&](int it) __attribute__((always_inline)) {
+    const int bi = it / maxch, ch = it - bi * maxch;
+    const DevBlock b = blocks[bi];
+    if (ch >= time_chunks(b.C, b.T, L)) return;
+    load_thresholds<INT>(b, P, sm);
+    phase_time<INT, L>(b, P, sm, ch);
+  });
+}
+
+// Phase B, frequency direction: column slabs of a block
+template <bool INT>
+__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_freq_kernel(const DevBlock* __restrict__ blocks, int nb,
+                                                                        int maxch, int* counter, DevParams P) {
+  __shared__ SmFreq<INT> sm;
+  run_items(nb * maxch, counter, [&](int it) __attribute__((always_inline)) {
+    const int bi = it / maxch, ch = it - bi * maxch;
+    const DevBlock b = blocks[bi];
+    if (ch >= freq_chunks(INT, b.C, b.T) || b.C <= 1 || P.nl_f <= 1) return;
+    load_thresholds<INT>(b, P, sm);
+    phase_freq<INT>(b, P, sm, ch);
+  });
+}
+
+// Phase C: SIR operator along time (rows in chunks), then along frequency (slabs)
+template <int L>
+__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_sir_time_kernel(const DevBlock* __restrict__ blocks, int nb,
+                                                                            int maxch, int* counter, DevParams P) {
+  __shared__ SmSirT sm;
+  run_items(nb * maxch, counter, [&](int it) __attribute__((always_inline)) {
+    const int bi = it / maxch, ch = it - bi * maxch;
+    const DevBlock b = blocks[bi];
+    if (ch >= time_chunks(b.C, b.T, L)) return;
+    phase_sir_time<L>(b, P, sm, ch);
+  });
+}
+
+__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_sir_freq_kernel(const DevBlock* __restrict__ blocks, int nb,
+                                                                            int maxch, int* counter, DevParams P) {
+  __shared__ SmSirF sm;
+  run_items(nb * maxch, counter, [&](int it) __attribute__((always_inline)) {
+    const int bi = it / maxch, ch = it - bi * maxch;
+    const DevBlock b = blocks[bi];
+    if (ch >= sirf_chunks(b.C, b.T)) return;
+    phase_sir_freq(b, P, sm, ch);
+  });
+}
+
+// Phase D: history flagger and flag bytes, rows in chunks of NW
+template <bool INT>
+__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_final_kernel(const DevBlock* __restrict__ blocks, int nb,
+                                                                         int maxch, int* counter, DevParams P) {
+  __shared__ SmFinal sm;
+  run_items(nb * maxch, counter, [&](int it) __attribute__((always_inline)) {
+    const int bi = it / maxch, ch = it - bi * maxch;
+    const DevBlock b = blocks[bi];
+    if (ch >= final_chunks(b.C)) return;
+    const int r0 = ch * NW, r1 = min(b.C, r0 + NW);
+    phase_history<INT>(b, P, sm, r0, r1);
+    phase_write(b, P, sm, r0, r1);
+  });
 }
 
 // zero a few device ints (work counters) without a memset node

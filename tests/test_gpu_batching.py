@@ -1,5 +1,5 @@
 """GPU: batched uneven blocks.  Results must not depend on the launch tuning
-(time layout per length bucket, one workgroup per block vs persistent grid),
+(time layout per length bucket, one workgroup per work item vs persistent grid),
 hipGraph replays must equal eager calls on every replay, and the autotuner must
 leave results unchanged."""
 import numpy as np
