@@ -9,10 +9,15 @@ time then frequency, SIR, history flagger against per-channel history of each
 (station, pol, subband) stream) and commits the staged history values with
 lof_history_update.  Inputs are resident in HBM before timing starts.
 
-Prints one JSON line.  `roofline` is for the flagging kernel: algorithmic bytes
-(input + one flag byte per sample + history ring traffic) per launch divided by
-its mean launch time measured with HIP events on the launch stream.
-`cpu_baseline` times the CPU reference on a bounded sample of the same blocks.
+Prints one JSON line.  `roofline` is for the dominant kernel of the path (the
+phase kernel with the largest share of a call): the bytes that phase must move
+per sample times the samples of a launch, divided by its mean launch time, from
+HIP events the library records on the launch stream between the phase kernels
+(LOF_OPT_PHASE_TIMING).  `path_roofline` is the whole call: input + one flag
+byte per sample + history ring traffic over the call's time.  `traffic` is the
+HBM traffic of that kernel from rocprofv3 counters (profiles/), or null when the
+kernel sources changed since the counters were taken.  `cpu_baseline` times the
+CPU reference on a bounded sample of the same blocks.
 """
 from __future__ import annotations
 
@@ -36,6 +41,44 @@ import synth  # noqa: E402
 C, T = synth.CFG1_C, synth.CFG1_T
 HBM_PEAK_GBS = 8000.0
 DEADLINE_S = T * (64.0 / 195.3125e3)   # 3072 samples of 327.68 us
+
+# kernel of each phase for this workload (complex int8, 48 samples per lane)
+DOMINANT_KERNEL = {"stats": "lof_stats_kernel<true>", "sumthreshold_time": "lof_time_kernel<true, 48>",
+                   "sumthreshold_freq": "lof_freq_kernel<true>", "sir_time": "lof_sir_time_kernel<48>",
+                   "sir_freq": "lof_sir_freq_kernel", "history_write": "lof_final_kernel<true>"}
+# bytes each phase must move per sample: 2 B of complex int8 input, 1 bit of mask
+# per read or write, 1 flag byte (history ring traffic is below 3% and left out)
+DOMINANT_BYTES_PER_SAMPLE = {"stats": 2.0, "sumthreshold_time": 2.125, "sumthreshold_freq": 2.25,
+                             "sir_time": 0.25, "sir_freq": 0.25, "history_write": 3.125}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_config1.txt")
+KERNEL_SOURCES = ("lof_device.hpp", "lof_kernels.hpp", "lof.hip")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1701_08197_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary (JSON
+    lines: kernel, fetch_bytes, write_bytes, source_hash), or None when absent
+    or taken from other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    cur = kernel_source_hash()
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            line = line.strip()
+            if not line.startswith("{"):
+                continue
+            rec = json.loads(line)
+            if rec.get("kernel") == kernel and rec.get("source_hash") == cur:
+                return int(rec["fetch_bytes"] + rec["write_bytes"])
+    return None
 
 
 def _gen_range(args):
@@ -274,7 +317,7 @@ def main():
     shm.unlink()
     flags = torch.empty((nb, C, T), dtype=torch.uint8, device=dev)
     prm = P.default_params(max_streams=nb, max_channels=C, max_blocks_per_call=nb,
-                           max_samples_per_call=nb * C * T)
+                           max_samples_per_call=nb * C * T, options=P.LOF_OPT_PHASE_TIMING)
     fl = P.Flagger(prm)
     arr = (NAT.LofBlock * nb)()
     for b in range(nb):
@@ -303,6 +346,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    fl.phase_times()          # drop the warm-up calls from the phase totals
     K = args.steps
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
@@ -315,6 +359,8 @@ def main():
         ends[k].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    phase_tot, phase_calls = fl.phase_times()
+    phase_ms = {k: v / max(1, phase_calls) for k, v in phase_tot.items()}
     kern_ms = [a.elapsed_time(b) for a, b in evs]
     # per-step latency: time from the step's launch to its completion
     step_ms = [evs[k][0].elapsed_time(ends[k]) for k in range(K)]
@@ -332,7 +378,13 @@ def main():
         hist_bytes.append(rd + nb * C * 8)
     alg_bytes = samples * 3 + statistics.mean(hist_bytes)
     kmean = statistics.mean(kern_ms)
-    achieved = alg_bytes / (kmean * 1e-3) / 1e9
+    path_achieved = alg_bytes / (kmean * 1e-3) / 1e9
+    # dominant kernel: the phase with the largest share of the call
+    dom = max(phase_ms, key=phase_ms.get)
+    dom_ms = phase_ms[dom]
+    dom_bytes = samples * DOMINANT_BYTES_PER_SAMPLE[dom]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    traffic = measured_traffic(DOMINANT_KERNEL[dom])
     lat = sorted(step_ms)
     p50 = lat[len(lat) // 2]
     p99 = lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]
@@ -358,9 +410,14 @@ def main():
                    "n_levels": prm.n_levels, "sir_eta": [prm.sir_eta_num, prm.sir_eta_den],
                    "history_len": H, "launch": "one lof_flag_blocks + one lof_history_update per step"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "lof_flag_kernel<int,48>", "kernel_ms": round(kmean, 4),
-                     "alg_bytes_per_launch": int(alg_bytes)},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": DOMINANT_KERNEL[dom], "kernel_ms": round(dom_ms, 4),
+                     "alg_bytes_per_launch": int(dom_bytes),
+                     "alg_bytes_per_sample": DOMINANT_BYTES_PER_SAMPLE[dom]},
+        "path_roofline": {"bound": "hbm", "achieved": round(path_achieved, 1), "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": round(path_achieved / HBM_PEAK_GBS, 4),
+                          "call_ms": round(kmean, 4), "alg_bytes_per_call": int(alg_bytes),
+                          "phases_ms": {k: round(v, 4) for k, v in phase_ms.items()}},
         "latency": {"p50_ms": round(p50, 3), "p99_ms": round(p99, 3),
                     "deadline_ms": round(DEADLINE_S * 1e3, 2), "unit": "ms per 6144-block second"},
         "gen_s": round(t_gen, 1),

@@ -68,6 +68,18 @@ typedef enum {
                                             is called again with the identical table and
                                             stats pointer (no descriptor upload, one
                                             graph launch)                                 */
+#define LOF_OPT_PHASE_TIMING 0x8u        /* record a HIP event after every phase kernel
+                                            of each lof_flag_blocks call, for
+                                            lof_phase_times (ignored with LOF_OPT_GRAPH) */
+
+/* Phases of the path, in launch order (lof_phase_times) */
+#define LOF_PHASE_STATS 0        /* power, median, stddev, thresholds (Sec. 2.1, 4.2)   */
+#define LOF_PHASE_ST_TIME 1      /* SumThreshold along time (Sec. 2.1)                  */
+#define LOF_PHASE_ST_FREQ 2      /* SumThreshold along frequency (Sec. 2.1)             */
+#define LOF_PHASE_SIR_TIME 3     /* SIR operator along time (Sec. 2.2)                  */
+#define LOF_PHASE_SIR_FREQ 4     /* SIR operator along frequency (Sec. 2.2)             */
+#define LOF_PHASE_FINAL 5        /* history flagger (Sec. 4.1) and flag bytes           */
+#define LOF_N_PHASES 6
 
 #define LOF_MAX_LEVELS 16
 #define LOF_MAX_CHANNELS 1024
@@ -189,6 +201,18 @@ lof_status lof_set_tuning(lof_ctx* ctx, const lof_tuning* tuning);
  * ids).  *out (host, nullable) receives the chosen tuning. */
 lof_status lof_autotune(lof_ctx* ctx, const lof_block* blocks, int32_t n_blocks, void* hip_stream,
                         int32_t reps, lof_tuning* out);
+
+/* Kernel time of each phase (LOF_PHASE_*), in milliseconds, summed over the
+ * lof_flag_blocks calls of ctx since the previous lof_phase_times (or since
+ * lof_create), into the HOST array ms[LOF_N_PHASES]; *n_calls receives the
+ * number of calls summed.  A phase launched for several block kinds or time
+ * layouts counts all its launches.  Each figure is the span between HIP events
+ * recorded on the call's stream around that phase's kernels.  Waits for the
+ * outstanding calls; resets the totals.  Needs LOF_OPT_PHASE_TIMING (calls made
+ * by lof_autotune are not counted).  Errors: LOF_ERR_INVALID when the option is
+ * off, ctx uses LOF_OPT_GRAPH or a pointer is NULL; LOF_ERR_DEVICE when an
+ * event query fails. */
+lof_status lof_phase_times(lof_ctx* ctx, double* ms, int32_t* n_calls);
 
 /* Frees the context.  The caller must have synchronised every stream used with
  * it.  NULL is a no-op. */

@@ -18,12 +18,16 @@ LOF_CI8, LOF_C64, LOF_F32, LOF_C64_AMP = 0, 1, 2, 3
 LOF_OPT_AUTOCOMMIT = 0x1
 LOF_OPT_LITERAL_HISTORY_TIE = 0x2
 LOF_OPT_GRAPH = 0x4
+LOF_OPT_PHASE_TIMING = 0x8
+# phases of lof_phase_times, in launch order
+PHASES = ("stats", "sumthreshold_time", "sumthreshold_freq", "sir_time", "sir_freq", "history_write")
+LOF_N_PHASES = len(PHASES)
 LOF_MAX_LEVELS = 16
 LOF_TUNE_BUCKETS = 5
 
 EXPORTED = ("lof_default_params", "lof_create", "lof_flag_blocks", "lof_history_update",
-            "lof_history_export", "lof_get_tuning", "lof_set_tuning", "lof_autotune", "lof_destroy",
-            "lof_last_error")
+            "lof_history_export", "lof_get_tuning", "lof_set_tuning", "lof_autotune", "lof_phase_times",
+            "lof_destroy", "lof_last_error")
 
 
 class LofParams(ctypes.Structure):
@@ -125,6 +129,8 @@ def load() -> ctypes.CDLL:
     L.lof_autotune.restype = ctypes.c_int
     L.lof_destroy.argtypes = [ctypes.c_void_p]
     L.lof_destroy.restype = ctypes.c_int
+    L.lof_phase_times.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+    L.lof_phase_times.restype = ctypes.c_int
     L.lof_last_error.argtypes = [ctypes.c_void_p]
     L.lof_last_error.restype = ctypes.c_char_p
     _lib = L

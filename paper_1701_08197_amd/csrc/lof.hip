@@ -35,7 +35,8 @@ constexpr int MAX_TIMES = lofk::SIR_SEG * lofk::SIR_MAX_SEGS;   // 262144
 
 thread_local const char* g_create_err = "no error";
 
-constexpr int NCOUNTER = 32;      // persistent-launch work counters per call (<= 18 launches)
+constexpr int NCOUNTER = 32;      // persistent-launch work counters per call (<= 20 launches)
+constexpr int NTEV = NCOUNTER + 1;   // phase-timing events per call
 
 struct Slot {
   DevBlock* d_desc = nullptr;
@@ -45,6 +46,12 @@ struct Slot {
   int* d_counter = nullptr;       // persistent-launch work counters, one per launch
   hipEvent_t ev = nullptr;
   bool used = false;
+  // LOF_OPT_PHASE_TIMING: event 0 before the first phase kernel, event k after
+  // launch k, whose phase is tph[k]
+  hipEvent_t tev[NTEV] = {};
+  int tph[NTEV] = {};
+  int ntev = 0;
+  bool timed = false;             // events of a call not yet added to the totals
 };
 
 int time_bucket(int T) { return T <= 1024 ? 0 : (T <= 2048 ? 1 : (T <= 3072 ? 2 : (T <= 4096 ? 3 : 4))); }
@@ -90,6 +97,8 @@ struct lof_ctx {
   int32_t call_no = 0;
   std::vector<DevBlock> tmp;
   std::vector<int> order;
+  double phase_ms[LOF_N_PHASES] = {};   // LOF_OPT_PHASE_TIMING totals since the last read
+  int32_t phase_calls = 0;
   const char* err = "no error";
 };
 
@@ -187,10 +196,15 @@ void free_slot(Slot& s) {
   if (s.d_state) (void)hipFree(s.d_state);
   if (s.d_counter) (void)hipFree(s.d_counter);
   if (s.ev) (void)hipEventDestroy(s.ev);
+  for (hipEvent_t& e : s.tev)
+    if (e) (void)hipEventDestroy(e);
   s = Slot();
 }
 
-bool alloc_slot(Slot& s, int max_blocks, size_t mask_words) {
+bool alloc_slot(Slot& s, int max_blocks, size_t mask_words, bool timing) {
+  if (timing)
+    for (hipEvent_t& e : s.tev)
+      if (hipEventCreate(&e) != hipSuccess) return false;
   return hipMalloc(&s.d_desc, sizeof(DevBlock) * max_blocks) == hipSuccess &&
          hipHostMalloc(&s.h_desc, sizeof(DevBlock) * max_blocks, hipHostMallocDefault) == hipSuccess &&
          hipMalloc(&s.d_mask, sizeof(uint64_t) * mask_words) == hipSuccess &&
@@ -300,8 +314,8 @@ void build_table(lof_ctx* c, const lof_tuning& t, const lof_block* blocks, int32
 }
 
 // one kernel launch over nb blocks (maxch > 0: chunked kernel, nb * maxch items)
-void launch(lof_ctx* c, const lof_tuning& t, int kid, const DevBlock* dd, int nb, int maxch, Slot& s, int& ncounter,
-            hipStream_t st, const DevParams& P) {
+void launch(lof_ctx* c, const lof_tuning& t, int kid, int phase, const DevBlock* dd, int nb, int maxch, Slot& s,
+            int& ncounter, hipStream_t st, const DevParams& P) {
   const int items = maxch > 0 ? nb * maxch : nb;
   if (items <= 0) return;
   int* counter = nullptr;
@@ -321,6 +335,10 @@ void launch(lof_ctx* c, const lof_tuning& t, int kid, const DevBlock* dd, int nb
     void* args[] = {&a_blocks, &a_nb, &a_counter, &a_p};
     (void)hipLaunchKernel(kernel_of(kid), dim3(grid), dim3(lofk::WG), args, 0, st);
   }
+  if (s.tev[0] && s.ntev > 0 && s.ntev < NTEV) {
+    s.tph[s.ntev] = phase;
+    (void)hipEventRecord(s.tev[s.ntev++], st);
+  }
 }
 
 template <class F>
@@ -333,9 +351,11 @@ int max_chunks(const DevBlock* h, int n, F&& f) {
 // kernels of one call on stream st (descriptors already on the device in s and
 // still in s.h_desc, which sizes the chunked launches)
 void enqueue(lof_ctx* c, const lof_tuning& t, Slot& s, const int* counts, int n, void* stats, hipStream_t st,
-             bool autocommit) {
+             bool autocommit, bool timing = false) {
   const DevParams P = dev_params(c, s.d_mask, s.d_state, stats);
   if (t.persistent) hipLaunchKernelGGL(lofk::lof_zero_kernel, dim3(1), dim3(64), 0, st, s.d_counter, NCOUNTER);
+  s.ntev = 0;
+  if (timing && s.tev[0] && hipEventRecord(s.tev[0], st) == hipSuccess) s.ntev = 1;
   int nc = 0;
   int off = 0;
   for (int kind = 0; kind < 2; ++kind) {
@@ -344,30 +364,47 @@ void enqueue(lof_ctx* c, const lof_tuning& t, Slot& s, const int* counts, int n,
     const bool integer = kind == 0;
     const DevBlock* dk = s.d_desc + off;
     const DevBlock* hk = s.h_desc + off;
-    launch(c, t, K_STATS + kind, dk, kcnt, 0, s, nc, st, P);
+    launch(c, t, K_STATS + kind, LOF_PHASE_STATS, dk, kcnt, 0, s, nc, st, P);
     int mt[3] = {0, 0, 0};
     for (int j = 0, voff = 0; j < 3; voff += counts[3 * kind + j], ++j) {
       const int cnt = counts[3 * kind + j];
       if (!cnt) continue;
       const int L = variant_lanes(j);
       mt[j] = max_chunks(hk + voff, cnt, [&](const DevBlock& b) { return lofk::time_chunks(b.C, b.T, L); });
-      launch(c, t, K_TIME + 3 * kind + j, dk + voff, cnt, mt[j], s, nc, st, P);
+      launch(c, t, K_TIME + 3 * kind + j, LOF_PHASE_ST_TIME, dk + voff, cnt, mt[j], s, nc, st, P);
     }
     const int mf = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::freq_chunks(integer, b.C, b.T); });
-    launch(c, t, K_FREQ + kind, dk, kcnt, mf, s, nc, st, P);
+    launch(c, t, K_FREQ + kind, LOF_PHASE_ST_FREQ, dk, kcnt, mf, s, nc, st, P);
     if (c->prm.sir_eta_num > 0) {
       for (int j = 0, voff = 0; j < 3; voff += counts[3 * kind + j], ++j) {
         const int cnt = counts[3 * kind + j];
-        if (cnt) launch(c, t, K_SIRT + j, dk + voff, cnt, mt[j], s, nc, st, P);
+        if (cnt) launch(c, t, K_SIRT + j, LOF_PHASE_SIR_TIME, dk + voff, cnt, mt[j], s, nc, st, P);
       }
       const int ms = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::sirf_chunks(b.C, b.T); });
-      launch(c, t, K_SIRF, dk, kcnt, ms, s, nc, st, P);
+      launch(c, t, K_SIRF, LOF_PHASE_SIR_FREQ, dk, kcnt, ms, s, nc, st, P);
     }
     const int mw = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::final_chunks(b.C); });
-    launch(c, t, K_FINAL + kind, dk, kcnt, mw, s, nc, st, P);
+    launch(c, t, K_FINAL + kind, LOF_PHASE_FINAL, dk, kcnt, mw, s, nc, st, P);
     off += kcnt;
   }
   if (autocommit) hipLaunchKernelGGL(lofk::lof_commit_desc_kernel, dim3(n), dim3(256), 0, st, s.d_desc, n, P);
+}
+
+// add a finished call's phase times (events of slot s) to the totals of ctx
+bool harvest_timing(lof_ctx* c, Slot& s) {
+  if (!s.timed || s.ntev < 2) {
+    s.timed = false;
+    return true;
+  }
+  s.timed = false;
+  if (hipEventSynchronize(s.tev[s.ntev - 1]) != hipSuccess) return false;
+  for (int k = 1; k < s.ntev; ++k) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, s.tev[k - 1], s.tev[k]) != hipSuccess) return false;
+    c->phase_ms[s.tph[k]] += t;
+  }
+  c->phase_calls++;
+  return true;
 }
 
 }  // namespace
@@ -452,9 +489,11 @@ lof_status lof_create(const lof_params* params, int hip_device, lof_ctx** out) {
   // mask scratch: one u64 word per 64 samples of a row, rows rounded up
   c->mask_words = (size_t)(params->max_samples_per_call / 64) +
                   (size_t)params->max_blocks_per_call * (size_t)params->max_channels + 64;
-  for (int i = 0; ok && i < NSLOT; ++i) ok = alloc_slot(c->slot[i], params->max_blocks_per_call, c->mask_words);
+  const bool timing = (params->options & LOF_OPT_PHASE_TIMING) && !(params->options & LOF_OPT_GRAPH);
+  for (int i = 0; ok && i < NSLOT; ++i)
+    ok = alloc_slot(c->slot[i], params->max_blocks_per_call, c->mask_words, timing);
   if (ok && (params->options & LOF_OPT_GRAPH)) {
-    ok = alloc_slot(c->gslot, params->max_blocks_per_call, c->mask_words) &&
+    ok = alloc_slot(c->gslot, params->max_blocks_per_call, c->mask_words, false) &&
          hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
   }
   if (ok) {
@@ -532,12 +571,15 @@ lof_status lof_flag_blocks(lof_ctx* c, const lof_block* blocks, int32_t n, void*
   if (s.used) {
     // the slot's previous call must be done before its table and scratch are reused
     if (hipEventSynchronize(s.ev) != hipSuccess) return fail(c, LOF_ERR_DEVICE, "hipEventSynchronize failed");
+    if (!harvest_timing(c, s)) return fail(c, LOF_ERR_DEVICE, "event timing failed");
   }
   build_table(c, c->tune, blocks, n, s, counts, true);
   if (hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(DevBlock) * n, hipMemcpyHostToDevice, st) != hipSuccess)
     return fail(c, LOF_ERR_DEVICE, "descriptor upload failed");
-  enqueue(c, c->tune, s, counts, n, stats, st, autocommit);
+  const bool timing = (c->prm.options & LOF_OPT_PHASE_TIMING) != 0;
+  enqueue(c, c->tune, s, counts, n, stats, st, autocommit, timing);
   if (hipGetLastError() != hipSuccess) return fail(c, LOF_ERR_DEVICE, "kernel launch failed");
+  s.timed = timing && s.ntev >= 2;
   if (hipEventRecord(s.ev, st) != hipSuccess) return fail(c, LOF_ERR_DEVICE, "hipEventRecord failed");
   s.used = true;
   return LOF_OK;
@@ -569,8 +611,10 @@ lof_status lof_autotune(lof_ctx* c, const lof_block* blocks, int32_t n, void* hi
   DevGuard g(c->dev);
   hipStream_t st = (hipStream_t)hip_stream;
   // wait for every slot: tuning uses slot 0 synchronously
-  for (auto& s : c->slot)
+  for (auto& s : c->slot) {
     if (s.used && hipEventSynchronize(s.ev) != hipSuccess) return fail(c, LOF_ERR_DEVICE, "slot wait failed");
+    if (!harvest_timing(c, s)) return fail(c, LOF_ERR_DEVICE, "event timing failed");
+  }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(c, LOF_ERR_DEVICE, "event creation failed");
@@ -701,6 +745,23 @@ lof_status lof_history_export(lof_ctx* c, double* values, int32_t* counts, doubl
       }
     }
   }
+  return LOF_OK;
+}
+
+lof_status lof_phase_times(lof_ctx* c, double* ms, int32_t* n_calls) {
+  if (!c) return LOF_ERR_INVALID;
+  if (!ms || !n_calls) return fail(c, LOF_ERR_INVALID, "ms or n_calls is NULL");
+  if (!(c->prm.options & LOF_OPT_PHASE_TIMING) || (c->prm.options & LOF_OPT_GRAPH))
+    return fail(c, LOF_ERR_INVALID, "phase timing needs LOF_OPT_PHASE_TIMING without LOF_OPT_GRAPH");
+  DevGuard g(c->dev);
+  for (auto& s : c->slot)
+    if (!harvest_timing(c, s)) return fail(c, LOF_ERR_DEVICE, "event timing failed");
+  for (int p = 0; p < LOF_N_PHASES; ++p) {
+    ms[p] = c->phase_ms[p];
+    c->phase_ms[p] = 0.0;
+  }
+  *n_calls = c->phase_calls;
+  c->phase_calls = 0;
   return LOF_OK;
 }
 

@@ -146,6 +146,15 @@ __device__ __forceinline__ uint64_t quad_next_64(uint64_t v) {
   return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
+// The thread index as a value the compiler cannot move.  The phases run inside a
+// work-item loop; values derived from a plain threadIdx.x would be hoisted out
+// of it and held, spilled to scratch, across every item.
+__device__ __forceinline__ int thread_id() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 __device__ __forceinline__ uint64_t lowmask(int n) {
   return n <= 0 ? 0ull : (n >= 64 ? ~0ull : ((1ull << n) - 1ull));
 }

@@ -36,7 +36,7 @@ struct FastDiv {
 // block-wide: bin holding `rank` (0-based) of a 4096-bin histogram
 template <class SM>
 __device__ void find_bin(const uint32_t* h, uint32_t rank, SM& sm, uint32_t& bin, uint32_t& rem) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
   constexpr int PER = HBINS / WG;
   uint32_t loc[PER];
   uint32_t s = 0;
@@ -78,7 +78,7 @@ __device__ void find_bin(const uint32_t* h, uint32_t rank, SM& sm, uint32_t& bin
 // thread t owns words [32t, 32t+32), the last thread also word 16384.
 template <class SM>
 __device__ uint32_t find_bin16(const uint32_t* h, uint32_t rank, SM& sm) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
   constexpr int PW = (IHIST_WORDS - 1) / WG;   // 32
   const int w0 = tid * PW;
   const int nw = PW + (tid == WG - 1 ? 1 : 0);
@@ -136,7 +136,7 @@ template <bool INT, class SM>
 __device__ __forceinline__ void radix_select(const DevBlock& b, SM& sm, uint32_t r0, uint32_t r1, bool have_pass0,
                              uint32_t& k0, uint32_t& k1) {
   typedef typename PowT<INT>::T VT;
-  const int tid = threadIdx.x;
+  const int tid = thread_id();
   const int nch = (b.T + 7) >> 3;
   const uint32_t items = (uint32_t)b.C * (uint32_t)nch;
   const FastDiv fd((uint32_t)nch);
@@ -188,7 +188,7 @@ __device__ __forceinline__ void radix_select(const DevBlock& b, SM& sm, uint32_t
 template <bool INT, class SM>
 __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& P, SM& sm) {
   typedef typename PowT<INT>::T VT;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
   const int nch = (b.T + 7) >> 3;
   const uint32_t items = (uint32_t)b.C * (uint32_t)nch;
   const FastDiv fd((uint32_t)nch);
@@ -342,7 +342,7 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
 // against the window word D = S*512 + 4c as G = floor(c*T_k)*512 + 511.
 template <bool INT, class SM>
 __device__ __forceinline__ void load_thresholds(const DevBlock& b, const DevParams& P, SM& sm) {
-  const int tid = threadIdx.x;
+  const int tid = thread_id();
   const GLB BlockState* bs = gp<const BlockState>(P.bstate) + b.sidx;
   if (tid < 16) {
     const double t = bs->T[tid];
@@ -574,7 +574,12 @@ __device__ __forceinline__ uint32_t px_fill(LD& ld, uint64_t fm, uint32_t (&Y)[L
   }
   const uint32_t off = incl - run;
 #pragma unroll
-  for (int i = 0; i < L; ++i) Y[i] += off;
+  for (int i = 0; i < L; ++i) {
+    Y[i] += off;
+    // opaque from here on: otherwise the compiler keeps the L loaded values
+    // alive to re-derive Y[i] - Y[i-1] later, which costs L registers
+    asm("" : "+v"(Y[i]));
+  }
   return off;
 }
 
@@ -616,12 +621,17 @@ __device__ __forceinline__ uint32_t push_bit(uint32_t acc, int32_t g, uint32_t d
   return __builtin_amdgcn_alignbit(acc, (uint32_t)(g - (int32_t)d), 31);
 }
 
+#ifndef LOF_PXB
+#define LOF_PXB 8
+#endif
+constexpr int PXB = LOF_PXB;   // windows per batch of table reads
+
 template <int L, int K, class SM>
 __device__ __forceinline__ void st_level_px(uint32_t (&Y)[L], uint32_t& yprev, uint64_t& fm, uint64_t& pend,
                                             const int lig, const int G, const int n, const int pos0,
                                             const uint64_t vmask, const SM& sm) {
   constexpr int I = 1 << K;
-  static_assert(I <= 2 * L && L % 16 == 0, "a window may reach at most two lanes ahead");
+  static_assert(I <= 2 * L && L % PXB == 0, "a window may reach at most two lanes ahead");
   if (__ballot(pend != 0) != 0) px_drop<L>(Y, yprev, pend, lig, G);
   pend = 0;
   const int nvw = n - I + 1 - pos0;
@@ -636,18 +646,18 @@ __device__ __forceinline__ void st_level_px(uint32_t (&Y)[L], uint32_t& yprev, u
       if (i >= 32) hi = push_bit(hi, g, d); else lo = push_bit(lo, g, d);
     }
   } else {
-    // sixteen windows at a time: all table reads in flight before they are used
+    // PXB windows at a time: their table reads in flight before they are used
 #pragma unroll
-    for (int i0 = L - 16; i0 >= 0; i0 -= 16) {
-      uint32_t d[16];
-      int32_t g[16];
+    for (int i0 = L - PXB; i0 >= 0; i0 -= PXB) {
+      uint32_t d[PXB];
+      int32_t g[PXB];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
+      for (int j = 0; j < PXB; ++j) {
         d[j] = px_win<L>(Y, yprev, i0 + j, I);
         g[j] = Gk[(d[j] >> 2) & 127u];
       }
 #pragma unroll
-      for (int j = 15; j >= 0; --j) {
+      for (int j = PXB - 1; j >= 0; --j) {
         if (i0 + j >= 32) hi = push_bit(hi, g[j], d[j]); else lo = push_bit(lo, g[j], d[j]);
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -831,7 +841,7 @@ __device__ __forceinline__ void or_bit_lds(uint64_t* w, int idx, int bit) {
 // ===================================================================== phase B
 template <bool INT, int L, class SM>
 __device__ __forceinline__ void phase_time(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
   const int T = b.T, C = b.C;
   const int W = (T + 63) >> 6;
   GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
@@ -840,8 +850,10 @@ __device__ __forceinline__ void phase_time(const DevBlock& b, const DevParams& P
     int G = 1;
     while (G * L < T) G <<= 1;
     const int R = 64 / G, lig = lane & (G - 1), grp = lane / G;
-    const int rend = (chunk + 1) * NW * R;
-    for (int rb = chunk * NW * R + wv * R; rb < C && rb < rend; rb += NW * R) {
+    // a chunk is NW * R rows: each wave takes its R rows once (no loop, so
+    // nothing is hoisted and held across rows)
+    const int rb = chunk * NW * R + wv * R;
+    if (rb < C) {
       const int row = rb + grp;
       const bool ok = row < C;
       TimeLoader<INT, L> ld{RowSrc(b), ok ? row : 0, lig * L, clampi(T - lig * L, 0, L), ok};
@@ -850,9 +862,11 @@ __device__ __forceinline__ void phase_time(const DevBlock& b, const DevParams& P
       else fm = st_core<INT, L>(ld, 0ull, lig, T, 0, nlev, sm);
       write_row_bits<L>(m0 + (int64_t)(ok ? row : 0) * W, W, fm, lig, G, ok);
     }
-  } else {
-    // long rows: segments of 64*L positions, SEG_CORE finished positions each
-    for (int row = chunk * NW + wv; row < C && row < (chunk + 1) * NW; row += NW) {
+  } else if constexpr (L == 64) {
+    // long rows (only laid out with L == 64): segments of 64*L positions,
+    // SEG_CORE finished positions each
+    const int row = chunk * NW + wv;
+    if (row < C) {
       for (int c0 = 0; c0 < T; c0 += SEG_CORE) {
         const int c1 = min(T, c0 + SEG_CORE);
         const int q0 = max(0, c0 - SEG_HALO);
@@ -892,7 +906,7 @@ template <bool INT, bool POWERS, class SM>
 __device__ __forceinline__ void stage_slab(const DevBlock& b, SM& sm, const GLB uint64_t* m0, int W, int it0, int ncols, int wb,
                            int nwl, int stride) {
   typedef typename PowT<INT>::T VT;
-  const int tid = threadIdx.x, C = b.C;
+  const int tid = thread_id(), C = b.C;
   const FastDiv fw((uint32_t)nwl);
   for (int i = tid; i < C * nwl; i += WG) {
     const int c = (int)fw.div((uint32_t)i), j = i - c * nwl;
@@ -914,7 +928,7 @@ __device__ __forceinline__ void stage_slab(const DevBlock& b, SM& sm, const GLB 
 
 template <bool INT, int LF, class SM>
 __device__ __forceinline__ void phase_freq_l(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
   const int T = b.T, C = b.C;
   const int W = (T + 63) >> 6;
   GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
@@ -995,13 +1009,13 @@ __device__ __forceinline__ void col_level(const uint16_t* tile, int stride, int 
     constexpr int NWIN = NC - I + 1;   // full windows of the column
     uint32_t lo = 0, hi = 0;
 #pragma unroll
-    for (int i0 = ((NWIN - 1) / 16) * 16; i0 >= 0; i0 -= 16) {
-      int32_t g[16];
+    for (int i0 = ((NWIN - 1) / PXB) * PXB; i0 >= 0; i0 -= PXB) {
+      int32_t g[PXB];
 #pragma unroll
-      for (int j = 0; j < 16; ++j)
+      for (int j = 0; j < PXB; ++j)
         if (i0 + j < NWIN) g[j] = Gk[(D[i0 + j < NWIN ? i0 + j : 0] >> 2) & 127u];
 #pragma unroll
-      for (int j = 15; j >= 0; --j) {
+      for (int j = PXB - 1; j >= 0; --j) {
         if (i0 + j < NWIN) {
           const uint32_t d = D[i0 + j < NWIN ? i0 + j : 0];
           if (i0 + j >= 32) hi = push_bit(hi, g[j], d); else lo = push_bit(lo, g[j], d);
@@ -1044,13 +1058,14 @@ __device__ __forceinline__ uint64_t st_col(const uint16_t* tile, int stride, int
 
 template <int NC, class SM>
 __device__ __forceinline__ void phase_freq_col(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
   const int T = b.T, C = NC;
   const int W = (T + 63) >> 6;
   GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
   const int nlev = min(P.nl_f, ST_MAX_LEVELS);
   constexpr int cpi = NW * 64, stride = cpi + 1;
-  for (int it0 = chunk * cpi; it0 < T && it0 < (chunk + 1) * cpi; it0 += cpi) {
+  const int it0 = chunk * cpi;   // one slab per chunk (no loop: nothing held across slabs)
+  if (it0 < T) {
     const int ncols = min(cpi, T - it0);
     const int wb = it0 >> 6;
     const int nwl = ((it0 + ncols - 1) >> 6) - wb + 1;
@@ -1179,7 +1194,7 @@ __device__ __forceinline__ uint64_t sir_lane_apply(uint64_t bits, int nval, int 
 
 template <int L, class SM>
 __device__ __forceinline__ void phase_sir_time(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
   const int T = b.T, C = b.C;
   const int W = (T + 63) >> 6;
   GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
@@ -1188,23 +1203,25 @@ __device__ __forceinline__ void phase_sir_time(const DevBlock& b, const DevParam
     int G = 1;
     while (G * L < T) G <<= 1;
     const int R = 64 / G, lig = lane & (G - 1), grp = lane / G;
-    const int rend = (chunk + 1) * NW * R;
-    for (int rb = chunk * NW * R + wv * R; rb < C && rb < rend; rb += NW * R) {
+    const int rb = chunk * NW * R + wv * R;   // this wave's R rows of the chunk
+    if (rb < C) {
       const int row = rb + grp;
       const bool ok = row < C;
       GLB uint64_t* rp = m0 + (int64_t)(ok ? row : 0) * W;
       const int nval = ok ? clampi(T - lig * L, 0, L) : 0;
       const uint64_t bits = ok ? (get_bits(rp, W, lig * L, L) & lowmask(nval)) : 0ull;
       const bool any = __ballot(bits != 0) != 0;
-      if (!any && num < den) continue;
-      const SirSum s = sir_lane_summary<L>(bits, nval, num, den);
-      int base, pmin, smax, gt, gn, gx;
-      sir_group_scan(s, lig, G, base, pmin, smax, gt, gn, gx);
-      const uint64_t out = sir_lane_apply<L>(bits, nval, num, den, base, pmin, smax);
-      write_row_bits<L>(rp, W, out, lig, G, ok);
+      if (any || num >= den) {   // nothing flagged and eta < 1: nothing to add
+        const SirSum s = sir_lane_summary<L>(bits, nval, num, den);
+        int base, pmin, smax, gt, gn, gx;
+        sir_group_scan(s, lig, G, base, pmin, smax, gt, gn, gx);
+        const uint64_t out = sir_lane_apply<L>(bits, nval, num, den, base, pmin, smax);
+        write_row_bits<L>(rp, W, out, lig, G, ok);
+      }
     }
-  } else {
-    // long rows (L == 64): SIR_SEG positions per segment, two passes with carries
+  } else if constexpr (L == 64) {
+    // long rows (only laid out with L == 64): SIR_SEG positions per segment, two
+    // passes with carries
     const int nseg = (T + SIR_SEG - 1) / SIR_SEG;
     int(*seg)[3] = sm.u.c.seg[wv];
     for (int row = chunk * NW + wv; row < C && row < (chunk + 1) * NW; row += NW) {
@@ -1263,7 +1280,7 @@ __device__ __forceinline__ void phase_sir_time(const DevBlock& b, const DevParam
 
 template <int LF, class SM>
 __device__ __forceinline__ void phase_sir_freq_l(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
   const int T = b.T, C = b.C;
   const int W = (T + 63) >> 6;
   GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
@@ -1324,7 +1341,7 @@ __device__ __forceinline__ void phase_sir_freq(const DevBlock& b, const DevParam
 template <bool INT, class SM>
 __device__ __forceinline__ void phase_history(const DevBlock& b, const DevParams& P, SM& sm, const int r0,
                                               const int r1) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
   const int T = b.T;
   const int W = (T + 63) >> 6;
   const GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
@@ -1415,7 +1432,7 @@ __device__ __forceinline__ void phase_history(const DevBlock& b, const DevParams
 // the caller's stats entry (zeroed by the statistics kernel).
 template <class SM>
 __device__ __forceinline__ void phase_write(const DevBlock& b, const DevParams& P, SM& sm, const int r0, const int r1) {
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = thread_id(), lane = tid & 63;
   const int T = b.T;
   const int W = (T + 63) >> 6;
   const GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
@@ -1464,6 +1481,10 @@ __device__ __forceinline__ void phase_write(const DevBlock& b, const DevParams& 
 #ifndef LOF_WAVES_PER_EU
 #define LOF_WAVES_PER_EU 4
 #endif
+// Float SumThreshold keeps sums and counts per position (twice the registers of
+// the packed integer form): 2 waves per SIMD, 256 VGPRs, no spills.  The float
+// frequency slab (81 KB of LDS) allows one workgroup per CU anyway.
+constexpr int float_waves_per_eu = 2;
 
 // A kernel's work items are (block, chunk) pairs, item = block * maxch + chunk;
 // chunks past a smaller block's count return at once.  With counter == nullptr
@@ -1471,18 +1492,20 @@ __device__ __forceinline__ void phase_write(const DevBlock& b, const DevParams& 
 // from a device counter until all are done.
 template <class F>
 __device__ __forceinline__ void run_items(int nitems, int* counter, F&& f) {
+  if (counter == nullptr) {
+    // one item per workgroup: a body with no loop around it, so nothing is
+    // hoisted and held across items
+    if ((int)blockIdx.x < nitems) f((int)blockIdx.x);
+    return;
+  }
   __shared__ int cur;
-  int it = (int)blockIdx.x;
   for (;;) {
-    if (counter != nullptr) {
-      if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
-      __syncthreads();
-      it = cur;
-      __syncthreads();
-    }
+    if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = cur;
+    __syncthreads();
     if (it >= nitems) break;
-    f(it);   // the one call site: always inlined
-    if (counter == nullptr) break;
+    f(it);
     __syncthreads();
   }
 }
@@ -1515,7 +1538,7 @@ __global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_stats_kernel(const D
 
 // Phase B, time direction: rows of a block in chunks
 template <bool INT, int L>
-__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_time_kernel(const DevBlock* __restrict__ blocks, int nb,
+__global__ __launch_bounds__(WG, INT ? LOF_WAVES_PER_EU : float_waves_per_eu) void lof_time_kernel(const DevBlock* __restrict__ blocks, int nb,
                                                                         int maxch, int* counter, DevParams P) {
   __shared__ SmThr sm;
   run_items(nb * maxch, counter, [&](int it) __attribute__((always_inline)) {
@@ -1529,7 +1552,7 @@ __global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_time_kernel(const De
 
 // Phase B, frequency direction: column slabs of a block
 template <bool INT>
-__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_freq_kernel(const DevBlock* __restrict__ blocks, int nb,
+__global__ __launch_bounds__(WG, INT ? LOF_WAVES_PER_EU : float_waves_per_eu) void lof_freq_kernel(const DevBlock* __restrict__ blocks, int nb,
                                                                         int maxch, int* counter, DevParams P) {
   __shared__ SmFreq<INT> sm;
   run_items(nb * maxch, counter, [&](int it) __attribute__((always_inline)) {

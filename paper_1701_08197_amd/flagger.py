@@ -144,6 +144,15 @@ class Flagger:
         self._check(self._L.lof_autotune(self._h, arr, n, _stream_handle(stream), reps, ctypes.byref(t)))
         return t
 
+    def phase_times(self):
+        """lof_phase_times: per-phase kernel milliseconds summed over the calls
+        since the previous read, and the number of calls (needs
+        LOF_OPT_PHASE_TIMING in the params' options)."""
+        arr = (ctypes.c_double * N.LOF_N_PHASES)()
+        n = ctypes.c_int32()
+        self._check(self._L.lof_phase_times(self._h, arr, ctypes.byref(n)))
+        return {name: float(arr[i]) for i, name in enumerate(N.PHASES)}, int(n.value)
+
     def close(self) -> None:
         if getattr(self, "_h", None):
             self._L.lof_destroy(self._h)
