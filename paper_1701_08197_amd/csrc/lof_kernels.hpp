@@ -644,6 +644,7 @@ __device__ __forceinline__ void st_level_px(uint32_t (&Y)[L], uint32_t& yprev, u
     for (int i = L - 1; i >= 0; --i) {
       const uint32_t d = px_win<L>(Y, yprev, i, I);
       if (i >= 32) hi = push_bit(hi, g, d); else lo = push_bit(lo, g, d);
+      if (i % PXB == 0) __builtin_amdgcn_sched_barrier(0);
     }
   } else {
     // PXB windows at a time: their table reads in flight before they are used
@@ -968,84 +969,135 @@ __device__ __forceinline__ void phase_freq_l(const DevBlock& b, const DevParams&
   }
 }
 
-// Integer input with exactly NC (16, 32 or 64) channels: one lane per column,
-// all NC channels in the lane, every loop bound known at compile time so only
-// full windows are summed and judged (no cross-lane traffic).
-template <int NC, class SM>
-__device__ __forceinline__ void col_fill(const uint16_t* tile, int stride, int col, bool ok, uint64_t fm,
-                                         uint32_t (&D)[NC]) {
+// 64 x 64 bit transpose across a wave (all 64 lanes take part): on entry lane r
+// holds row r (bit c = column c), on exit lane c holds column c (bit r = row r).
+// Stage s trades with lane r ^ s and swaps the off-diagonal s x s blocks.
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, int lane) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int s = 32 >> k;
+    const uint64_t m = k == 0 ? 0x00000000FFFFFFFFull
+                     : k == 1 ? 0x0000FFFF0000FFFFull
+                     : k == 2 ? 0x00FF00FF00FF00FFull
+                     : k == 3 ? 0x0F0F0F0F0F0F0F0Full
+                     : k == 4 ? 0x3333333333333333ull
+                              : 0x5555555555555555ull;
+    const uint32_t ylo = __shfl_xor((unsigned)(uint32_t)x, s);
+    const uint32_t yhi = __shfl_xor((unsigned)(uint32_t)(x >> 32), s);
+    const uint64_t y = ((uint64_t)yhi << 32) | ylo;
+    x = (lane & s) ? ((x & ~m) | ((y & ~m) >> s)) : ((x & m) | ((y & m) << s));
+  }
+  return x;
+}
+
+// Integer input with exactly NC (16, 32 or 64) channels.  A wave takes 64
+// columns, i.e. one mask word of every channel: lane c reads channel c's word
+// and a bit transpose gives every lane its column's channel mask.  The lane
+// loads its column straight from global memory (each 2-byte load instruction
+// reads 128 contiguous bytes across the wave) and keeps inclusive prefix sums
+// Q[i] of the packed words, as the time rows do, with every window inside the
+// lane: Q[i + I - 1] - Q[i - 1].  Newly flagged channels are removed from the
+// prefixes in registers; the new flags go back through the transpose, one
+// store per channel word.
+template <int NC>
+__device__ __forceinline__ void col_drop(uint32_t (&Q)[NC], uint64_t drop) {
+  const uint32_t dlo = (uint32_t)drop, dhi = (uint32_t)(drop >> 32);
+  uint32_t run = 0, prev = 0;
 #pragma unroll
   for (int i = 0; i < NC; ++i) {
-    const uint32_t p = tile[i * stride + col];
-    const bool live = ok && !((fm >> i) & 1ull);
-    D[i] = live ? p * 512u + 4u : 0u;
-    if ((i & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+    const uint32_t y = Q[i];
+    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)(i < 32 ? dlo : dhi), i & 31, 1);
+    run += (y - prev) & m;
+    prev = y;
+    Q[i] = y - run;
   }
 }
 
-template <int NC, int M>
-__device__ __forceinline__ void col_rebuild(uint32_t (&D)[NC]) {
-  // D = S_1 -> S_{2^M}: step j sums windows of 2^(j+1) from halves 2^j
-#pragma unroll
-  for (int j = 0; j < M; ++j) {
-    const int h = 1 << j;
-#pragma unroll
-    for (int i = 0; i + 2 * h <= NC; ++i) D[i] += D[i + h];
-  }
+template <int NC>
+__device__ __forceinline__ uint32_t col_win(const uint32_t (&Q)[NC], int i, int I) {
+  const uint32_t hi = Q[(i + I - 1 < NC) ? i + I - 1 : 0];
+  return i == 0 ? hi : hi - Q[(i > 0) ? i - 1 : 0];
 }
 
 template <int NC, int K, class SM>
-__device__ __forceinline__ void col_level(const uint16_t* tile, int stride, int col, bool ok, uint32_t (&D)[NC],
-                                          uint64_t& fm, bool& dirty, const SM& sm) {
+__device__ __forceinline__ void col_level_px(uint32_t (&Q)[NC], uint64_t& fm, uint64_t& pend, const bool ok,
+                                             const SM& sm) {
   constexpr int I = 1 << K;
   if constexpr (I <= NC) {
-    if (dirty) {
-      col_fill<NC, SM>(tile, stride, col, ok, fm, D);
-      col_rebuild<NC, K - 1>(D);
-    }
-#pragma unroll
-    for (int i = 0; i + I <= NC; ++i) D[i] += D[i + I / 2];
+    if (__ballot(pend != 0) != 0) col_drop<NC>(Q, pend);
+    pend = 0;
     const int32_t* Gk = sm.G[K];
     constexpr int NWIN = NC - I + 1;   // full windows of the column
     uint32_t lo = 0, hi = 0;
+    // (one path for every wave: a second, scalar-threshold branch over the same
+    // window differences makes the compiler compute them all ahead of the branch)
 #pragma unroll
     for (int i0 = ((NWIN - 1) / PXB) * PXB; i0 >= 0; i0 -= PXB) {
+      uint32_t d[PXB];
       int32_t g[PXB];
 #pragma unroll
-      for (int j = 0; j < PXB; ++j)
-        if (i0 + j < NWIN) g[j] = Gk[(D[i0 + j < NWIN ? i0 + j : 0] >> 2) & 127u];
+      for (int j = 0; j < PXB; ++j) {
+        if (i0 + j < NWIN) {
+          d[j] = col_win<NC>(Q, i0 + j, I);
+          g[j] = Gk[(d[j] >> 2) & 127u];
+        }
+      }
 #pragma unroll
       for (int j = PXB - 1; j >= 0; --j) {
         if (i0 + j < NWIN) {
-          const uint32_t d = D[i0 + j < NWIN ? i0 + j : 0];
-          if (i0 + j >= 32) hi = push_bit(hi, g[j], d); else lo = push_bit(lo, g[j], d);
+          if (i0 + j >= 32) hi = push_bit(hi, g[j], d[j]); else lo = push_bit(lo, g[j], d[j]);
         }
       }
       __builtin_amdgcn_sched_barrier(0);
     }
     uint64_t wf = (uint64_t)lo | ((uint64_t)hi << 32);
     if (!ok) wf = 0;
-    if (__ballot(wf != 0) == 0) {
-      dirty = false;
-      return;
-    }
+    if (__ballot(wf != 0) == 0) return;
     uint64_t nb = wf;
 #pragma unroll
     for (int d = 1; d < I; d <<= 1) nb |= nb << d;
     nb &= lowmask(NC);
-    const uint64_t changed = nb & ~fm;
+    pend = nb & ~fm;
     fm |= nb;
-    dirty = __ballot(changed != 0) != 0;
   }
 }
 
 template <int NC, class SM>
-__device__ __forceinline__ uint64_t st_col(const uint16_t* tile, int stride, int col, bool ok, uint64_t fm, int nlev, const SM& sm) {
-  uint32_t D[NC];
-  col_fill<NC, SM>(tile, stride, col, ok, fm, D);
-  bool dirty = false;
+__device__ __forceinline__ void phase_freq_col(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
+  const int T = b.T;
+  const int W = (T + 63) >> 6;
+  GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
+  const int nlev = min(P.nl_f, ST_MAX_LEVELS);
+  const int word = chunk * NW + wv;   // this wave's 64 columns (wave-uniform)
+  if (word >= W) return;
+  const int t = word * 64 + lane;
+  const bool ok = t < T;
+  const uint64_t rw = lane < NC ? ld_mask(m0 + (int64_t)lane * W + word) : 0ull;
+  uint64_t fm = wave_transpose64(rw, lane);
+  fm = ok ? (fm & lowmask(NC)) : 0ull;
+  const uint64_t fm0 = fm;
+  const GLB uint16_t* col = gp<const uint16_t>(b.data) + (ok ? t : 0);
+  uint32_t Q[NC];
+  uint32_t run = 0;
+#pragma unroll
+  for (int i0 = 0; i0 < NC; i0 += 16) {
+    uint32_t w[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) w[j] = col[(int64_t)(i0 + j) * b.dstride];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int i = i0 + j;
+      const uint32_t v = (ok && !((fm >> i) & 1ull)) ? ci8_power(w[j]) * 512u + 4u : 0u;
+      run += v;
+      Q[i] = run;
+      asm("" : "+v"(Q[i]));   // opaque: the loaded values need not stay alive
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  uint64_t pend = 0;
 #define LOF_CLEVEL(K) \
-  if (K < nlev) col_level<NC, K>(tile, stride, col, ok, D, fm, dirty, sm);
+  if (K < nlev) col_level_px<NC, K>(Q, fm, pend, ok, sm);
   LOF_CLEVEL(1)
   LOF_CLEVEL(2)
   LOF_CLEVEL(3)
@@ -1053,50 +1105,10 @@ __device__ __forceinline__ uint64_t st_col(const uint16_t* tile, int stride, int
   LOF_CLEVEL(5)
   LOF_CLEVEL(6)
 #undef LOF_CLEVEL
-  return fm;
-}
-
-template <int NC, class SM>
-__device__ __forceinline__ void phase_freq_col(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
-  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
-  const int T = b.T, C = NC;
-  const int W = (T + 63) >> 6;
-  GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
-  const int nlev = min(P.nl_f, ST_MAX_LEVELS);
-  constexpr int cpi = NW * 64, stride = cpi + 1;
-  const int it0 = chunk * cpi;   // one slab per chunk (no loop: nothing held across slabs)
-  if (it0 < T) {
-    const int ncols = min(cpi, T - it0);
-    const int wb = it0 >> 6;
-    const int nwl = ((it0 + ncols - 1) >> 6) - wb + 1;
-    stage_slab<true, true>(b, sm, m0, W, it0, ncols, wb, nwl, stride);
-    __syncthreads();
-    const int col = wv * 64 + lane;
-    const bool ok = col < ncols;
-    const int wsel = wv;   // it0 is a multiple of 64: wave w owns word wb + w
-    uint64_t fm0 = 0;
-    if (wsel < nwl) {
-#pragma unroll 4
-      for (int i = 0; i < NC; ++i) fm0 |= ((sm.u.f.w[i * nwl + wsel] >> lane) & 1ull) << i;
-    }
-    if (!ok) fm0 = 0;
-    const uint64_t fm = st_col<NC>(sm.u.f.t, stride, ok ? col : 0, ok, fm0, nlev, sm);
-    const uint64_t nb = ok ? (fm & ~fm0) : 0ull;
-    if (__ballot(nb != 0) != 0) {
-      // one wave owns one word per channel: rebuild it with ballots
-#pragma unroll
-      for (int i = 0; i < NC; ++i) {
-        const unsigned long long word = __ballot((int)((nb >> i) & 1ull));
-        if (lane == 0 && word != 0) sm.u.f.w[i * nwl + wsel] |= word;
-      }
-    }
-    __syncthreads();
-    for (int i = tid; i < C * nwl; i += WG) {
-      const int c = i / nwl, j = i - c * nwl;
-      m0[(int64_t)c * W + wb + j] = sm.u.f.w[i];
-    }
-    __syncthreads();
-  }
+  const uint64_t nbits = ok ? (fm & ~fm0) : 0ull;
+  if (__ballot(nbits != 0) == 0) return;
+  const uint64_t rnew = wave_transpose64(nbits, lane);
+  if (lane < NC && rnew != 0) m0[(int64_t)lane * W + word] = rw | rnew;
 }
 
 template <bool INT, class SM>
