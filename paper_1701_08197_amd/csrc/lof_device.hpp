@@ -105,7 +105,12 @@ __host__ __device__ inline int freq_chunks(bool integer, int C, int T) {
   const int span = freq_span(integer, C);
   return (T + span - 1) / span;
 }
-__host__ __device__ inline int sirf_chunks(int C, int T) { return freq_chunks(false, C, T); }
+// SIR along frequency: up to 64 channels one lane per column, 64 columns per wave
+__host__ __device__ inline bool sirf_colpath(int C) { return C <= 64; }
+__host__ __device__ inline int sirf_chunks(int C, int T) {
+  const int span = sirf_colpath(C) ? NW * 64 : freq_span(false, C);
+  return (T + span - 1) / span;
+}
 __host__ __device__ inline int final_chunks(int C) { return (C + NW - 1) / NW; }
 
 struct DevParams {

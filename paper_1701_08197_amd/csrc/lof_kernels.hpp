@@ -1338,12 +1338,105 @@ __device__ __forceinline__ void phase_sir_freq_l(const DevBlock& b, const DevPar
   }
 }
 
+// SIR on one lane's whole sequence of n <= 64 positions (bit i = position i
+// flagged), run by run.  With weights a = num (flagged) and -c = num - den
+// (unflagged), a maximal stretch [s, e) of unflagged positions has alpha, the
+// best sum (>= 0) of an interval ending at s - 1, and beta, the best sum (>= 0)
+// of an interval starting at e; its position s + j is flagged iff some interval
+// through it sums to >= 0, i.e. iff j < floor(alpha/c), or j >= len - floor(beta/c),
+// or alpha + beta >= len*c.  alpha and beta follow the runs: m flagged positions
+// add m*a, a stretch of len positions takes x to max(0, x - len*c).  At most
+// SIR_RUNS stretches per lane; returns false (out untouched) when there are more.
+constexpr int SIR_RUNS = 16;
+__device__ __forceinline__ bool sir_runs_lane(uint64_t bits, int n, int a, int c, const FastDiv& fc,
+                                              uint64_t& out_bits) {
+  const uint64_t vm = lowmask(n);
+  bits &= vm;
+  const uint64_t z = ~bits & vm;
+  uint64_t out = bits;
+  uint32_t sl[SIR_RUNS];   // stretch start | length << 8
+  int al[SIR_RUNS];
+  int K = 0, alpha = 0, pos = 0;
+  bool more = bits != 0 && z != 0;   // no flags or no gaps: nothing to add
+#pragma unroll
+  for (int k = 0; k < SIR_RUNS; ++k) {
+    if (__ballot(more) == 0) break;
+    if (more) {
+      const uint64_t rest = z >> pos;
+      if (rest == 0) {
+        more = false;
+      } else {
+        const int m = __builtin_ctzll(rest);
+        alpha += m * a;
+        pos += m;
+        const int len = __builtin_ctzll(~(z >> pos));
+        sl[k] = (uint32_t)pos | ((uint32_t)len << 8);
+        al[k] = alpha;
+        const int P = min(len, (int)fc.div((uint32_t)alpha));
+        out |= lowmask(P) << pos;
+        alpha = max(0, alpha - len * c);
+        pos += len;
+        K = k + 1;
+        if (pos >= n) more = false;
+      }
+    }
+  }
+  if (more && (z >> pos) != 0) return false;
+  int beta = 0, nxt = n;
+#pragma unroll
+  for (int k = SIR_RUNS - 1; k >= 0; --k) {
+    if (__ballot(k < K) == 0) continue;
+    if (k < K) {
+      const int st = (int)(sl[k] & 255u), len = (int)(sl[k] >> 8), e = st + len;
+      beta += (nxt - e) * a;
+      const int Q = min(len, (int)fc.div((uint32_t)beta));
+      out |= lowmask(Q) << (e - Q);
+      if (al[k] + beta >= len * c) out |= lowmask(len) << st;
+      beta = max(0, beta - len * c);
+      nxt = st;
+    }
+  }
+  out_bits = out;
+  return true;
+}
+
+// Up to 64 channels: a wave takes 64 columns (one mask word per channel), the
+// transpose gives each lane its whole column, SIR runs in the lane, and the new
+// flags go back through the transpose.
+__device__ __forceinline__ void phase_sir_freq_col(const DevBlock& b, const DevParams& P, const int chunk) {
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
+  const int T = b.T, C = b.C;
+  const int W = (T + 63) >> 6;
+  GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
+  const int num = P.eta_num, den = P.eta_den;
+  const int word = chunk * NW + wv;   // wave-uniform
+  if (word >= W || num == 0) return;
+  const int t = word * 64 + lane;
+  const bool ok = t < T;
+  const uint64_t rw = lane < C ? ld_mask(m0 + (int64_t)lane * W + word) : 0ull;
+  uint64_t bits = wave_transpose64(rw, lane);
+  bits = ok ? (bits & lowmask(C)) : 0ull;
+  if (__ballot(bits != 0) == 0) return;   // nothing flagged in these 64 columns
+  uint64_t out = bits;
+  if (num >= den) {
+    out = ok ? lowmask(C) : 0ull;   // eta = 1: every interval qualifies
+  } else {
+    const FastDiv fc((uint32_t)(den - num));
+    if (!sir_runs_lane(bits, C, num, den - num, fc, out))
+      out = sir_lane_apply<64>(bits, C, num, den, 0, BIG, -BIG);
+  }
+  const uint64_t nb = ok ? (out & ~bits) : 0ull;
+  if (__ballot(nb != 0) == 0) return;
+  const uint64_t rnew = wave_transpose64(nb, lane);
+  if (lane < C && rnew != 0) m0[(int64_t)lane * W + word] = rw | rnew;
+}
+
 template <class SM>
 __device__ __forceinline__ void phase_sir_freq(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
   const int C = b.C;
   if (C <= 1) return;
-  if (C <= 16) phase_sir_freq_l<16>(b, P, sm, chunk);
-  else phase_sir_freq_l<32>(b, P, sm, chunk);
+  if (sirf_colpath(C)) return phase_sir_freq_col(b, P, chunk);
+  phase_sir_freq_l<32>(b, P, sm, chunk);
 }
 
 // ===================================================================== phase D
