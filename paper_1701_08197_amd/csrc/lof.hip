@@ -43,6 +43,7 @@ struct Slot {
   DevBlock* h_desc = nullptr;     // pinned
   uint64_t* d_mask = nullptr;
   BlockState* d_state = nullptr;
+  uint64_t* d_rowsum = nullptr;   // integer rows' power sums [block][max_channels]
   int* d_counter = nullptr;       // persistent-launch work counters, one per launch
   hipEvent_t ev = nullptr;
   bool used = false;
@@ -115,7 +116,7 @@ struct DevGuard {
   }
 };
 
-DevParams dev_params(const lof_ctx* c, uint64_t* mask, BlockState* state, void* stats) {
+DevParams dev_params(const lof_ctx* c, uint64_t* mask, BlockState* state, uint64_t* rowsum, void* stats) {
   DevParams P;
   P.start = c->prm.start_threshold;
   P.p = c->prm.p;
@@ -136,6 +137,7 @@ DevParams dev_params(const lof_ctx* c, uint64_t* mask, BlockState* state, void* 
   P.pvalid = c->pvalid;
   P.maskw = mask;
   P.bstate = state;
+  P.rowsum = rowsum;
   P.stats = stats;
   return P;
 }
@@ -194,6 +196,7 @@ void free_slot(Slot& s) {
   if (s.h_desc) (void)hipHostFree(s.h_desc);
   if (s.d_mask) (void)hipFree(s.d_mask);
   if (s.d_state) (void)hipFree(s.d_state);
+  if (s.d_rowsum) (void)hipFree(s.d_rowsum);
   if (s.d_counter) (void)hipFree(s.d_counter);
   if (s.ev) (void)hipEventDestroy(s.ev);
   for (hipEvent_t& e : s.tev)
@@ -201,7 +204,7 @@ void free_slot(Slot& s) {
   s = Slot();
 }
 
-bool alloc_slot(Slot& s, int max_blocks, size_t mask_words, bool timing) {
+bool alloc_slot(Slot& s, int max_blocks, int max_channels, size_t mask_words, bool timing) {
   if (timing)
     for (hipEvent_t& e : s.tev)
       if (hipEventCreate(&e) != hipSuccess) return false;
@@ -209,6 +212,7 @@ bool alloc_slot(Slot& s, int max_blocks, size_t mask_words, bool timing) {
          hipHostMalloc(&s.h_desc, sizeof(DevBlock) * max_blocks, hipHostMallocDefault) == hipSuccess &&
          hipMalloc(&s.d_mask, sizeof(uint64_t) * mask_words) == hipSuccess &&
          hipMalloc(&s.d_state, sizeof(BlockState) * max_blocks) == hipSuccess &&
+         hipMalloc(&s.d_rowsum, sizeof(uint64_t) * (size_t)max_blocks * (size_t)max_channels) == hipSuccess &&
          hipMalloc(&s.d_counter, sizeof(int) * NCOUNTER) == hipSuccess &&
          hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) == hipSuccess;
 }
@@ -352,7 +356,7 @@ int max_chunks(const DevBlock* h, int n, F&& f) {
 // still in s.h_desc, which sizes the chunked launches)
 void enqueue(lof_ctx* c, const lof_tuning& t, Slot& s, const int* counts, int n, void* stats, hipStream_t st,
              bool autocommit, bool timing = false) {
-  const DevParams P = dev_params(c, s.d_mask, s.d_state, stats);
+  const DevParams P = dev_params(c, s.d_mask, s.d_state, s.d_rowsum, stats);
   if (t.persistent) hipLaunchKernelGGL(lofk::lof_zero_kernel, dim3(1), dim3(64), 0, st, s.d_counter, NCOUNTER);
   s.ntev = 0;
   if (timing && s.tev[0] && hipEventRecord(s.tev[0], st) == hipSuccess) s.ntev = 1;
@@ -491,9 +495,9 @@ lof_status lof_create(const lof_params* params, int hip_device, lof_ctx** out) {
                   (size_t)params->max_blocks_per_call * (size_t)params->max_channels + 64;
   const bool timing = (params->options & LOF_OPT_PHASE_TIMING) && !(params->options & LOF_OPT_GRAPH);
   for (int i = 0; ok && i < NSLOT; ++i)
-    ok = alloc_slot(c->slot[i], params->max_blocks_per_call, c->mask_words, timing);
+    ok = alloc_slot(c->slot[i], params->max_blocks_per_call, params->max_channels, c->mask_words, timing);
   if (ok && (params->options & LOF_OPT_GRAPH)) {
-    ok = alloc_slot(c->gslot, params->max_blocks_per_call, c->mask_words, false) &&
+    ok = alloc_slot(c->gslot, params->max_blocks_per_call, params->max_channels, c->mask_words, false) &&
          hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
   }
   if (ok) {
@@ -692,7 +696,7 @@ lof_status lof_history_update(lof_ctx* c, const int32_t* ids, int32_t n, void* h
   }
   DevGuard g(c->dev);
   hipStream_t st = (hipStream_t)hip_stream;
-  const DevParams P = dev_params(c, nullptr, nullptr, nullptr);
+  const DevParams P = dev_params(c, nullptr, nullptr, nullptr, nullptr);
   const int TPB = 256;
   if (!ids) {
     lofk::IdList none;

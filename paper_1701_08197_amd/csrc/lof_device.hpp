@@ -123,6 +123,7 @@ struct DevParams {
   uint8_t* pvalid;       // [streams][maxC]
   uint64_t* maskw;       // mask scratch of this call
   BlockState* bstate;    // per-block statistics of this call
+  uint64_t* rowsum;      // integer input: [block sidx][maxC] power sum of each row
   void* stats;           // lof_block_stats* or null
 };
 
@@ -158,6 +159,14 @@ __device__ __forceinline__ int thread_id() {
   int t = (int)threadIdx.x;
   asm volatile("" : "+v"(t));
   return t;
+}
+
+// lane q's double (q wave-uniform), read without memory
+__device__ __forceinline__ double lane_double(double x, int q) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, q);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), q);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 __device__ __forceinline__ uint64_t lowmask(int n) {

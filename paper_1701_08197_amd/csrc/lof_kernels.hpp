@@ -558,7 +558,8 @@ __device__ __forceinline__ uint32_t px_win(const uint32_t (&Y)[L], uint32_t ypre
 
 // v under mask fm -> prefixes; returns Y(-1)
 template <int L, class LD>
-__device__ __forceinline__ uint32_t px_fill(LD& ld, uint64_t fm, uint32_t (&Y)[L], int lig, int G) {
+__device__ __forceinline__ uint32_t px_fill(LD& ld, uint64_t fm, uint32_t (&Y)[L], int lig, int G,
+                                            uint32_t& lane_total) {
   float unused[L];
   ld.fill(fm, Y, unused);
   uint32_t run = 0;
@@ -567,6 +568,7 @@ __device__ __forceinline__ uint32_t px_fill(LD& ld, uint64_t fm, uint32_t (&Y)[L
     run += Y[i];
     Y[i] = run;
   }
+  lane_total = run;
   uint32_t incl = run;
   for (int d = 1; d < G; d <<= 1) {
     const uint32_t y = __shfl_up(incl, d, G);
@@ -672,16 +674,28 @@ __device__ __forceinline__ void st_level_px(uint32_t (&Y)[L], uint32_t& yprev, u
   fm |= nb;
 }
 
+// psum: the power sum of the lane's samples (the first fill runs with no flags:
+// its lane total is 512 * sum(p) + 4 * nval, exactly, below 2^31)
 template <int L, class LD, class SM>
 __device__ __forceinline__ uint64_t st_core_px(LD& ld, uint64_t fm, const int lig, const int G, const int n,
-                                               const int nlev, const SM& sm) {
+                                               const int nlev, const SM& sm, uint32_t& psum,
+                                               GLB uint64_t* row_sum = nullptr) {
   uint32_t Y[L];
   const int pos0 = lig * L;
   const int nval = clampi(n - pos0, 0, L);
   const uint64_t vmask = lowmask(nval);
   int kend = 0;
   while (kend < nlev && (1 << kend) <= n) ++kend;   // levels with I <= n
-  uint32_t yprev = px_fill<L>(ld, fm, Y, lig, G);
+  uint32_t lane_total;
+  uint32_t yprev = px_fill<L>(ld, fm, Y, lig, G, lane_total);
+  psum = (lane_total - 4u * (uint32_t)nval) >> 9;
+  if (row_sum != nullptr) {
+    // the row's power sum (exact) for the history flagger, stored now so that
+    // nothing extra stays live through the levels
+    uint32_t rs = psum;
+    for (int d = G >> 1; d >= 1; d >>= 1) rs += __shfl_xor(rs, d, G);
+    if (ld.ok && lig == 0) *row_sum = rs;
+  }
   uint64_t pend = 0;
 #define LOF_PLEVEL(K) \
   if (K < kend) st_level_px<L, K>(Y, yprev, fm, pend, lig, G, n, pos0, vmask, sm);
@@ -859,8 +873,13 @@ __device__ __forceinline__ void phase_time(const DevBlock& b, const DevParams& P
       const bool ok = row < C;
       TimeLoader<INT, L> ld{RowSrc(b), ok ? row : 0, lig * L, clampi(T - lig * L, 0, L), ok};
       uint64_t fm;
-      if constexpr (INT) fm = st_core_px<L>(ld, 0ull, lig, G, T, nlev, sm);
-      else fm = st_core<INT, L>(ld, 0ull, lig, T, 0, nlev, sm);
+      if constexpr (INT) {
+        uint32_t psum;
+        fm = st_core_px<L>(ld, 0ull, lig, G, T, nlev, sm, psum,
+                           gp<uint64_t>(P.rowsum) + (int64_t)b.sidx * P.maxC + (ok ? row : 0));
+      } else {
+        fm = st_core<INT, L>(ld, 0ull, lig, T, 0, nlev, sm);
+      }
       write_row_bits<L>(m0 + (int64_t)(ok ? row : 0) * W, W, fm, lig, G, ok);
     }
   } else if constexpr (L == 64) {
@@ -868,17 +887,27 @@ __device__ __forceinline__ void phase_time(const DevBlock& b, const DevParams& P
     // SEG_CORE finished positions each
     const int row = chunk * NW + wv;
     if (row < C) {
+      uint64_t rsum = 0;
       for (int c0 = 0; c0 < T; c0 += SEG_CORE) {
         const int c1 = min(T, c0 + SEG_CORE);
         const int q0 = max(0, c0 - SEG_HALO);
         const int n = min(T, q0 + 64 * L) - q0;
         TimeLoader<INT, L> ld{RowSrc(b), row, q0 + lane * L, clampi(n - lane * L, 0, L), true};
         uint64_t fm;
-        if constexpr (INT) fm = st_core_px<L>(ld, 0ull, lane, 64, n, nlev, sm);
-        else fm = st_core<INT, L>(ld, 0ull, lane, n, 0, nlev, sm);
         const int pos = q0 + lane * L;   // L == 64: one word per lane
-        if (L == 64 && pos >= c0 && pos < c1) m0[(int64_t)row * W + (pos >> 6)] = fm;
+        const bool core = pos >= c0 && pos < c1;
+        if constexpr (INT) {
+          uint32_t psum;
+          fm = st_core_px<L>(ld, 0ull, lane, 64, n, nlev, sm, psum);
+          if (!core) psum = 0;
+          for (int d = 32; d >= 1; d >>= 1) psum += __shfl_xor(psum, d);   // < 2^27 per segment
+          rsum += psum;
+        } else {
+          fm = st_core<INT, L>(ld, 0ull, lane, n, 0, nlev, sm);
+        }
+        if (core) m0[(int64_t)row * W + (pos >> 6)] = fm;
       }
+      if (INT && lane == 0) gp<uint64_t>(P.rowsum)[(int64_t)b.sidx * P.maxC + row] = rsum;
     }
   }
 }
@@ -1455,48 +1484,99 @@ __device__ __forceinline__ void phase_history(const DevBlock& b, const DevParams
     __syncthreads();
     return;
   }
-  typedef typename PowT<INT>::T VT;
-  const int nch = (T + 7) >> 3;
-  for (int row = r0 + wv; row < r1; row += NW) {
-    unsigned long long su = 0;
-    double sd = 0.0;
-    int cnt = 0;
-    const bool fast = b.aligned && (T & 7) == 0;
-    for (int c = lane; c < nch; c += 64) {
-      const int t0 = c * 8;
-      const uint64_t w = ld_mask(m0 + (int64_t)row * W + (t0 >> 6));
-      const uint32_t fb = (uint32_t)(w >> (t0 & 63)) & 0xffu;
-      VT v[8];
-      int nv = 8;
-      if (fast) load8v<INT>(b, row, t0, v);
-      else nv = load8<INT>(b, row, t0, v);
+  if constexpr (INT) {
+    // unflagged sum = the row's power sum (exact, from the time pass) minus the
+    // flagged samples' power: input is read only for mask words with flags
+    for (int row = r0 + wv; row < r1; row += NW) {
+      const GLB uint64_t* mrow = m0 + (int64_t)row * W;
+      const GLB uint8_t* rbase = gp<const uint8_t>(b.data) + (int64_t)row * b.dstride * 2;
+      uint32_t sf = 0;   // < 64 words * 64 * 32768 = 2^27 per lane
+      int nf = 0;
+      for (int wi = lane; wi < W; wi += 64) {
+        const int t0 = wi * 64;
+        const int nv = min(64, T - t0);
+        const uint64_t fw = ld_mask(mrow + wi) & lowmask(nv);
+        nf += __popcll(fw);
+        if (fw == 0) continue;
+        const GLB uint8_t* rb = rbase + (int64_t)t0 * 2;
+        if (b.aligned && nv == 64) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        if (j < nv && !((fb >> j) & 1u)) {
-          if (INT) su += (uint32_t)v[j];
-          else sd += (double)v[j];
-          ++cnt;
+          for (int j = 0; j < 8; ++j) {
+            const u32x4 q = *(const GLB u32x4*)(rb + 16 * j);
+            const uint32_t a4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+              const int i0 = 8 * j + 2 * m;
+              const uint32_t f = (uint32_t)(fw >> i0);
+              sf += (f & 1u) ? ci8_power(a4[m] & 0xffffu) : 0u;
+              sf += (f & 2u) ? ci8_power(a4[m] >> 16) : 0u;
+            }
+          }
+        } else {
+          uint64_t bits = fw;
+          while (bits) {
+            const int i = __builtin_ctzll(bits);
+            bits &= bits - 1;
+            sf += ci8_power(*(const GLB uint16_t*)(rb + 2 * i));
+          }
         }
       }
-    }
+      unsigned long long sfl = sf;
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-      su += __shfl_xor(su, d);
-      sd += __shfl_xor(sd, d);
-      cnt += __shfl_xor(cnt, d);
+      for (int d = 32; d >= 1; d >>= 1) {
+        sfl += __shfl_xor(sfl, d);
+        nf += __shfl_xor(nf, d);
+      }
+      if (lane == 0) {
+        const uint64_t tot = gp<const uint64_t>(P.rowsum)[(int64_t)b.sidx * P.maxC + row];
+        sm.u.c.rsum[row] = (double)(tot - sfl);   // integer sums < 2^53: exact
+        sm.u.c.rcnt[row] = T - nf;
+      }
     }
-    if (lane == 0) {
-      sm.u.c.rsum[row] = INT ? (double)su : sd;   // integer sums < 2^53: exact
-      sm.u.c.rcnt[row] = cnt;
+  } else {
+    const int nch = (T + 7) >> 3;
+    for (int row = r0 + wv; row < r1; row += NW) {
+      double sd = 0.0;
+      int cnt = 0;
+      const bool fast = b.aligned && (T & 7) == 0;
+      for (int c = lane; c < nch; c += 64) {
+        const int t0 = c * 8;
+        const uint64_t w = ld_mask(m0 + (int64_t)row * W + (t0 >> 6));
+        const uint32_t fb = (uint32_t)(w >> (t0 & 63)) & 0xffu;
+        float v[8];
+        int nv = 8;
+        if (fast) load8v<false>(b, row, t0, v);
+        else nv = load8<false>(b, row, t0, v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          if (j < nv && !((fb >> j) & 1u)) {
+            sd += (double)v[j];
+            ++cnt;
+          }
+        }
+      }
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) {
+        sd += __shfl_xor(sd, d);
+        cnt += __shfl_xor(cnt, d);
+      }
+      if (lane == 0) {
+        sm.u.c.rsum[row] = sd;
+        sm.u.c.rcnt[row] = cnt;
+      }
     }
   }
   __syncthreads();
+  // ring statistics of the chunk's rows, one wave per row: every lane loads one
+  // ring entry (one coalesced load per 64 entries), and the sums run in ring
+  // order, oldest first, one entry at a time over values read across lanes, as
+  // the sequential definition has them
   const int s = b.stream_id;
-  for (int row = r0 + tid; row < r1; row += WG) {
+  for (int row = r0 + wv; row < r1; row += NW) {
     const int64_t idx = (int64_t)s * P.maxC + row;
     const int cnt = sm.u.c.rcnt[row];
     if (cnt == 0) {
-      gp<uint8_t>(P.pvalid)[idx] = 0;
+      if (lane == 0) gp<uint8_t>(P.pvalid)[idx] = 0;
       continue;
     }
     const double cur = sm.u.c.rsum[row] / (double)cnt;
@@ -1507,27 +1587,37 @@ __device__ __forceinline__ void phase_history(const DevBlock& b, const DevParams
       const int head = gp<const int32_t>(P.rhead)[idx];
       const GLB double* ring = gp<const double>(P.ring) + idx * P.H;
       double acc = 0.0;
-      for (int j = 0; j < L; ++j) {
+      for (int j0 = 0; j0 < L; j0 += 64) {
+        const int j = j0 + lane;
         int k = head - L + j;
         if (k < 0) k += P.H;
-        acc += ring[k];
+        const double x = j < L ? ring[k] : 0.0;
+        const int m = min(64, L - j0);
+        for (int q = 0; q < m; ++q) acc += lane_double(x, q);
       }
       const double hm = acc / (double)L;
       acc = 0.0;
-      for (int j = 0; j < L; ++j) {
+      for (int j0 = 0; j0 < L; j0 += 64) {
+        const int j = j0 + lane;
         int k = head - L + j;
         if (k < 0) k += P.H;
-        const double d = ring[k] - hm;
-        acc += d * d;
+        const double x = j < L ? ring[k] : 0.0;
+        const int m = min(64, L - j0);
+        for (int q = 0; q < m; ++q) {
+          const double d = lane_double(x, q) - hm;
+          acc += d * d;
+        }
       }
       const double hv = acc / (double)L;
       const double thr = hm + P.hs * __builtin_sqrt(hv);
       flag = P.literal ? (cur >= thr) : (cur > thr);
       if (flag) pushv = thr;
     }
-    gp<double>(P.pend)[idx] = pushv;
-    gp<uint8_t>(P.pvalid)[idx] = 1;
-    if (flag) atomicOr(&sm.rowflag[row >> 5], 1u << (row & 31));
+    if (lane == 0) {
+      gp<double>(P.pend)[idx] = pushv;
+      gp<uint8_t>(P.pvalid)[idx] = 1;
+      if (flag) atomicOr(&sm.rowflag[row >> 5], 1u << (row & 31));
+    }
   }
   __syncthreads();
 }
