@@ -364,12 +364,6 @@ struct SmSirF {
 };
 
 struct SmFinal {
-  union {
-    struct {
-      double rsum[MAXC];          // per-row unflagged sum
-      int32_t rcnt[MAXC];         // per-row unflagged count
-    } c;
-  } u;
   uint32_t rowflag[MAXC / 32];
   unsigned long long red_u[2][NW];
 };

@@ -1429,9 +1429,33 @@ __device__ __forceinline__ bool sir_runs_lane(uint64_t bits, int n, int a, int c
   return true;
 }
 
+// flag bytes of one row word: nv (<= 64) samples from t0, bit j -> byte j
+__device__ __forceinline__ void write_word_bytes(const DevBlock& b, int row, int t0, int nv, uint64_t w) {
+  GLB uint8_t* fp = gp<uint8_t>(b.flags) + (int64_t)row * b.fstride + t0;
+  if (b.faligned && nv == 64) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t h = (uint32_t)(w >> (16 * q)) & 0xffffu;
+      uint32_t o[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t nib = (h >> (4 * j)) & 0xfu;
+        o[j] = (nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21);
+      }
+      *(GLB u32x4*)(fp + 16 * q) = u32x4{o[0], o[1], o[2], o[3]};
+    }
+  } else {
+    for (int j = 0; j < nv; ++j) fp[j] = (uint8_t)((w >> j) & 1ull);
+  }
+}
+
 // Up to 64 channels: a wave takes 64 columns (one mask word per channel), the
 // transpose gives each lane its whole column, SIR runs in the lane, and the new
-// flags go back through the transpose.
+// flags go back through the transpose.  This is the last pass over the mask, so
+// it also writes the flag bytes of its 64 columns (the history pass rewrites
+// only rows it flags) and counts the flagged samples.
+__host__ __device__ inline bool sirf_writes_bytes(int eta_num, int C) { return eta_num > 0 && C > 1 && C <= 64; }
+
 __device__ __forceinline__ void phase_sir_freq_col(const DevBlock& b, const DevParams& P, const int chunk) {
   const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
   const int T = b.T, C = b.C;
@@ -1442,22 +1466,35 @@ __device__ __forceinline__ void phase_sir_freq_col(const DevBlock& b, const DevP
   if (word >= W || num == 0) return;
   const int t = word * 64 + lane;
   const bool ok = t < T;
+  const int nv = min(64, T - word * 64);
   const uint64_t rw = lane < C ? ld_mask(m0 + (int64_t)lane * W + word) : 0ull;
+  uint64_t rnew = 0;
   uint64_t bits = wave_transpose64(rw, lane);
   bits = ok ? (bits & lowmask(C)) : 0ull;
-  if (__ballot(bits != 0) == 0) return;   // nothing flagged in these 64 columns
-  uint64_t out = bits;
-  if (num >= den) {
-    out = ok ? lowmask(C) : 0ull;   // eta = 1: every interval qualifies
-  } else {
-    const FastDiv fc((uint32_t)(den - num));
-    if (!sir_runs_lane(bits, C, num, den - num, fc, out))
-      out = sir_lane_apply<64>(bits, C, num, den, 0, BIG, -BIG);
+  if (__ballot(bits != 0) != 0) {
+    uint64_t out = bits;
+    if (num >= den) {
+      out = ok ? lowmask(C) : 0ull;   // eta = 1: every interval qualifies
+    } else {
+      const FastDiv fc((uint32_t)(den - num));
+      if (!sir_runs_lane(bits, C, num, den - num, fc, out))
+        out = sir_lane_apply<64>(bits, C, num, den, 0, BIG, -BIG);
+    }
+    const uint64_t nb = ok ? (out & ~bits) : 0ull;
+    if (__ballot(nb != 0) != 0) {
+      rnew = wave_transpose64(nb, lane);
+      if (lane < C && rnew != 0) m0[(int64_t)lane * W + word] = rw | rnew;
+    }
   }
-  const uint64_t nb = ok ? (out & ~bits) : 0ull;
-  if (__ballot(nb != 0) == 0) return;
-  const uint64_t rnew = wave_transpose64(nb, lane);
-  if (lane < C && rnew != 0) m0[(int64_t)lane * W + word] = rw | rnew;
+  const uint64_t fw = (rw | rnew) & lowmask(nv);
+  if (lane < C) write_word_bytes(b, lane, word * 64, nv, fw);
+  if (P.stats) {
+    unsigned long long nfl = lane < C ? (unsigned long long)__popcll(fw) : 0ull;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) nfl += __shfl_xor(nfl, d);
+    char* st = (char*)P.stats + (int64_t)b.out_idx * (int64_t)(18 * 8 + 16);
+    if (lane == 0 && nfl) atomicAdd((unsigned long long*)(st + 18 * 8), nfl);
+  }
 }
 
 template <class SM>
@@ -1471,152 +1508,154 @@ __device__ __forceinline__ void phase_sir_freq(const DevBlock& b, const DevParam
 // ===================================================================== phase D
 // History flagger (Sec. 4.1) on the rows [r0, r1) of a block: per channel, the
 // mean of this block's unflagged samples against mean + history_sensitivity *
-// stddev of the committed means.
+// stddev of the committed means.  One wave per row; the ring's state does not
+// depend on this block, so its loads are issued first and overlap the loads of
+// the row's mask and samples.
+template <bool INT>
+__device__ __forceinline__ void row_unflagged(const DevBlock& b, const DevParams& P, int row, int lane, double& usum,
+                                              int& cnt) {
+  const int T = b.T;
+  const int W = (T + 63) >> 6;
+  const GLB uint64_t* mrow = gp<uint64_t>(P.maskw) + b.mask_off + (int64_t)row * W;
+  if constexpr (INT) {
+    // the row's power sum (exact, from the time pass) minus the flagged
+    // samples' power: input is read only for mask words with flags
+    const GLB uint8_t* rbase = gp<const uint8_t>(b.data) + (int64_t)row * b.dstride * 2;
+    uint32_t sf = 0;   // < 64 words * 64 * 32768 = 2^27 per lane
+    int nf = 0;
+    for (int wi = lane; wi < W; wi += 64) {
+      const int t0 = wi * 64;
+      const int nv = min(64, T - t0);
+      const uint64_t fw = ld_mask(mrow + wi) & lowmask(nv);
+      nf += __popcll(fw);
+      if (fw == 0) continue;
+      const GLB uint8_t* rb = rbase + (int64_t)t0 * 2;
+      if (b.aligned && nv == 64) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const u32x4 q = *(const GLB u32x4*)(rb + 16 * j);
+          const uint32_t a4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const uint32_t f = (uint32_t)(fw >> (8 * j + 2 * m));
+            sf += (f & 1u) ? ci8_power(a4[m] & 0xffffu) : 0u;
+            sf += (f & 2u) ? ci8_power(a4[m] >> 16) : 0u;
+          }
+        }
+      } else {
+        uint64_t bits = fw;
+        while (bits) {
+          const int i = __builtin_ctzll(bits);
+          bits &= bits - 1;
+          sf += ci8_power(*(const GLB uint16_t*)(rb + 2 * i));
+        }
+      }
+    }
+    unsigned long long sfl = sf;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      sfl += __shfl_xor(sfl, d);
+      nf += __shfl_xor(nf, d);
+    }
+    const uint64_t tot = gp<const uint64_t>(P.rowsum)[(int64_t)b.sidx * P.maxC + row];
+    usum = (double)(tot - sfl);   // integer sums < 2^53: exact
+    cnt = T - nf;
+  } else {
+    const int nch = (T + 7) >> 3;
+    double sd = 0.0;
+    int c = 0;
+    const bool fast = b.aligned && (T & 7) == 0;
+    for (int ci = lane; ci < nch; ci += 64) {
+      const int t0 = ci * 8;
+      const uint32_t fb = (uint32_t)(ld_mask(mrow + (t0 >> 6)) >> (t0 & 63)) & 0xffu;
+      float v[8];
+      int nv = 8;
+      if (fast) load8v<false>(b, row, t0, v);
+      else nv = load8<false>(b, row, t0, v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (j < nv && !((fb >> j) & 1u)) {
+          sd += (double)v[j];
+          ++c;
+        }
+      }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      sd += __shfl_xor(sd, d);
+      c += __shfl_xor(c, d);
+    }
+    usum = sd;
+    cnt = c;
+  }
+}
+
 template <bool INT, class SM>
 __device__ __forceinline__ void phase_history(const DevBlock& b, const DevParams& P, SM& sm, const int r0,
                                               const int r1) {
   const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
-  const int T = b.T;
-  const int W = (T + 63) >> 6;
-  const GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
   for (int i = tid; i < MAXC / 32; i += WG) sm.rowflag[i] = 0u;
-  if (b.stream_id < 0) {
-    __syncthreads();
-    return;
-  }
-  if constexpr (INT) {
-    // unflagged sum = the row's power sum (exact, from the time pass) minus the
-    // flagged samples' power: input is read only for mask words with flags
-    for (int row = r0 + wv; row < r1; row += NW) {
-      const GLB uint64_t* mrow = m0 + (int64_t)row * W;
-      const GLB uint8_t* rbase = gp<const uint8_t>(b.data) + (int64_t)row * b.dstride * 2;
-      uint32_t sf = 0;   // < 64 words * 64 * 32768 = 2^27 per lane
-      int nf = 0;
-      for (int wi = lane; wi < W; wi += 64) {
-        const int t0 = wi * 64;
-        const int nv = min(64, T - t0);
-        const uint64_t fw = ld_mask(mrow + wi) & lowmask(nv);
-        nf += __popcll(fw);
-        if (fw == 0) continue;
-        const GLB uint8_t* rb = rbase + (int64_t)t0 * 2;
-        if (b.aligned && nv == 64) {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const u32x4 q = *(const GLB u32x4*)(rb + 16 * j);
-            const uint32_t a4[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-              const int i0 = 8 * j + 2 * m;
-              const uint32_t f = (uint32_t)(fw >> i0);
-              sf += (f & 1u) ? ci8_power(a4[m] & 0xffffu) : 0u;
-              sf += (f & 2u) ? ci8_power(a4[m] >> 16) : 0u;
-            }
-          }
-        } else {
-          uint64_t bits = fw;
-          while (bits) {
-            const int i = __builtin_ctzll(bits);
-            bits &= bits - 1;
-            sf += ci8_power(*(const GLB uint16_t*)(rb + 2 * i));
-          }
-        }
-      }
-      unsigned long long sfl = sf;
-#pragma unroll
-      for (int d = 32; d >= 1; d >>= 1) {
-        sfl += __shfl_xor(sfl, d);
-        nf += __shfl_xor(nf, d);
-      }
-      if (lane == 0) {
-        const uint64_t tot = gp<const uint64_t>(P.rowsum)[(int64_t)b.sidx * P.maxC + row];
-        sm.u.c.rsum[row] = (double)(tot - sfl);   // integer sums < 2^53: exact
-        sm.u.c.rcnt[row] = T - nf;
-      }
-    }
-  } else {
-    const int nch = (T + 7) >> 3;
-    for (int row = r0 + wv; row < r1; row += NW) {
-      double sd = 0.0;
-      int cnt = 0;
-      const bool fast = b.aligned && (T & 7) == 0;
-      for (int c = lane; c < nch; c += 64) {
-        const int t0 = c * 8;
-        const uint64_t w = ld_mask(m0 + (int64_t)row * W + (t0 >> 6));
-        const uint32_t fb = (uint32_t)(w >> (t0 & 63)) & 0xffu;
-        float v[8];
-        int nv = 8;
-        if (fast) load8v<false>(b, row, t0, v);
-        else nv = load8<false>(b, row, t0, v);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          if (j < nv && !((fb >> j) & 1u)) {
-            sd += (double)v[j];
-            ++cnt;
-          }
-        }
-      }
-#pragma unroll
-      for (int d = 32; d >= 1; d >>= 1) {
-        sd += __shfl_xor(sd, d);
-        cnt += __shfl_xor(cnt, d);
-      }
-      if (lane == 0) {
-        sm.u.c.rsum[row] = sd;
-        sm.u.c.rcnt[row] = cnt;
-      }
-    }
-  }
   __syncthreads();
-  // ring statistics of the chunk's rows, one wave per row: every lane loads one
-  // ring entry (one coalesced load per 64 entries), and the sums run in ring
-  // order, oldest first, one entry at a time over values read across lanes, as
-  // the sequential definition has them
   const int s = b.stream_id;
-  for (int row = r0 + wv; row < r1; row += NW) {
+  const int row = r0 + wv;   // one row per wave (a chunk is NW rows)
+  if (s >= 0 && row < r1) {
     const int64_t idx = (int64_t)s * P.maxC + row;
-    const int cnt = sm.u.c.rcnt[row];
+    const int L = gp<const int32_t>(P.rcount)[idx];
+    const int head = gp<const int32_t>(P.rhead)[idx];
+    const GLB double* ring = gp<const double>(P.ring) + idx * P.H;
+    const bool judge = L >= P.Hmin;
+    // the first 64 entries in ring order, oldest first (lane j holds entry j)
+    int k0 = head - L + lane;
+    if (k0 < 0) k0 += P.H;
+    const double x0 = (judge && lane < L) ? ring[k0] : 0.0;
+    double usum;
+    int cnt;
+    row_unflagged<INT>(b, P, row, lane, usum, cnt);
     if (cnt == 0) {
       if (lane == 0) gp<uint8_t>(P.pvalid)[idx] = 0;
-      continue;
-    }
-    const double cur = sm.u.c.rsum[row] / (double)cnt;
-    const int L = gp<const int32_t>(P.rcount)[idx];
-    bool flag = false;
-    double pushv = cur;
-    if (L >= P.Hmin) {
-      const int head = gp<const int32_t>(P.rhead)[idx];
-      const GLB double* ring = gp<const double>(P.ring) + idx * P.H;
-      double acc = 0.0;
-      for (int j0 = 0; j0 < L; j0 += 64) {
-        const int j = j0 + lane;
-        int k = head - L + j;
-        if (k < 0) k += P.H;
-        const double x = j < L ? ring[k] : 0.0;
-        const int m = min(64, L - j0);
-        for (int q = 0; q < m; ++q) acc += lane_double(x, q);
-      }
-      const double hm = acc / (double)L;
-      acc = 0.0;
-      for (int j0 = 0; j0 < L; j0 += 64) {
-        const int j = j0 + lane;
-        int k = head - L + j;
-        if (k < 0) k += P.H;
-        const double x = j < L ? ring[k] : 0.0;
-        const int m = min(64, L - j0);
-        for (int q = 0; q < m; ++q) {
-          const double d = lane_double(x, q) - hm;
-          acc += d * d;
+    } else {
+      const double cur = usum / (double)cnt;
+      bool flag = false;
+      double pushv = cur;
+      if (judge) {
+        // sums in ring order, one entry at a time over values read across
+        // lanes, as the sequential definition has them
+        double acc = 0.0;
+        for (int j0 = 0; j0 < L; j0 += 64) {
+          double x = x0;
+          if (j0 > 0) {
+            int k = head - L + j0 + lane;
+            if (k < 0) k += P.H;
+            x = j0 + lane < L ? ring[k] : 0.0;
+          }
+          const int m = min(64, L - j0);
+          for (int q = 0; q < m; ++q) acc += lane_double(x, q);
         }
+        const double hm = acc / (double)L;
+        acc = 0.0;
+        for (int j0 = 0; j0 < L; j0 += 64) {
+          double x = x0;
+          if (j0 > 0) {
+            int k = head - L + j0 + lane;
+            if (k < 0) k += P.H;
+            x = j0 + lane < L ? ring[k] : 0.0;
+          }
+          const int m = min(64, L - j0);
+          for (int q = 0; q < m; ++q) {
+            const double d = lane_double(x, q) - hm;
+            acc += d * d;
+          }
+        }
+        const double hv = acc / (double)L;
+        const double thr = hm + P.hs * __builtin_sqrt(hv);
+        flag = P.literal ? (cur >= thr) : (cur > thr);
+        if (flag) pushv = thr;
       }
-      const double hv = acc / (double)L;
-      const double thr = hm + P.hs * __builtin_sqrt(hv);
-      flag = P.literal ? (cur >= thr) : (cur > thr);
-      if (flag) pushv = thr;
-    }
-    if (lane == 0) {
-      gp<double>(P.pend)[idx] = pushv;
-      gp<uint8_t>(P.pvalid)[idx] = 1;
-      if (flag) atomicOr(&sm.rowflag[row >> 5], 1u << (row & 31));
+      if (lane == 0) {
+        gp<double>(P.pend)[idx] = pushv;
+        gp<uint8_t>(P.pvalid)[idx] = 1;
+        if (flag) atomicOr(&sm.rowflag[row >> 5], 1u << (row & 31));
+      }
     }
   }
   __syncthreads();
@@ -1625,8 +1664,11 @@ __device__ __forceinline__ void phase_history(const DevBlock& b, const DevParams
 // final flags of the rows [r0, r1) = SIR mask OR history rows; one byte per
 // sample.  The block's flagged-sample and history-row totals are accumulated in
 // the caller's stats entry (zeroed by the statistics kernel).
+// With bytes_done the SIR pass already wrote and counted the SIR flags: only
+// rows the history flags are rewritten (all ones) and their extra flags counted.
 template <class SM>
-__device__ __forceinline__ void phase_write(const DevBlock& b, const DevParams& P, SM& sm, const int r0, const int r1) {
+__device__ __forceinline__ void phase_write(const DevBlock& b, const DevParams& P, SM& sm, const int r0, const int r1,
+                                            const bool bytes_done) {
   const int tid = thread_id(), lane = tid & 63;
   const int T = b.T;
   const int W = (T + 63) >> 6;
@@ -1639,12 +1681,20 @@ __device__ __forceinline__ void phase_write(const DevBlock& b, const DevParams& 
     const int rr = (int)fd.div(it);
     const int row = r0 + rr;
     const int t0 = (int)(it - (uint32_t)rr * (uint32_t)nch) * 16;
+    const bool hrow = (sm.rowflag[row >> 5] >> (row & 31)) & 1u;
+    if (bytes_done && !hrow) continue;
     const uint64_t w = ld_mask(m0 + (int64_t)row * W + (t0 >> 6));
     uint32_t fb = (uint32_t)(w >> (t0 & 63)) & 0xffffu;
-    if ((sm.rowflag[row >> 5] >> (row & 31)) & 1u) fb = 0xffffu;
     const int nv = min(16, T - t0);
-    fb &= (nv >= 16) ? 0xffffu : ((1u << nv) - 1u);
-    nfl += (unsigned long long)__builtin_popcount(fb);
+    const uint32_t vm16 = (nv >= 16) ? 0xffffu : ((1u << nv) - 1u);
+    fb &= vm16;
+    if (hrow) {
+      nfl += (unsigned long long)__builtin_popcount(vm16 & ~fb);   // added by the history flag
+      if (!bytes_done) nfl += (unsigned long long)__builtin_popcount(fb);
+      fb = vm16;
+    } else {
+      nfl += (unsigned long long)__builtin_popcount(fb);
+    }
     GLB uint8_t* fp = gp<uint8_t>(b.flags) + (int64_t)row * b.fstride + t0;
     if (b.faligned && nv == 16) {
       uint32_t o[4];
@@ -1794,7 +1844,7 @@ __global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_final_kernel(const D
     if (ch >= final_chunks(b.C)) return;
     const int r0 = ch * NW, r1 = min(b.C, r0 + NW);
     phase_history<INT>(b, P, sm, r0, r1);
-    phase_write(b, P, sm, r0, r1);
+    phase_write(b, P, sm, r0, r1, sirf_writes_bytes(P.eta_num, b.C));
   });
 }
 
