@@ -1233,6 +1233,127 @@ __device__ __forceinline__ uint64_t sir_lane_apply(uint64_t bits, int nval, int 
   return ((uint64_t)lo | ((uint64_t)hi << 32)) & vm;
 }
 
+// SIR on one lane's sequence of n <= 64 positions (bit i = position i flagged),
+// run by run.  With weights a = num (flagged) and -c = num - den (unflagged), a
+// maximal stretch [s, e) of unflagged positions has alpha, the best sum (>= 0)
+// of an interval ending at s - 1, and beta, the best sum (>= 0) of an interval
+// starting at e; its position s + j is flagged iff some interval through it sums
+// to >= 0, i.e. iff j < floor(alpha/c), or j >= len - floor(beta/c), or
+// alpha + beta >= len*c.  alpha and beta follow the runs: m flagged positions add
+// m*a, a stretch of len positions takes x to max(0, x - len*c).  alpha0 / beta0
+// are the best sums of intervals ending just before position 0 and starting just
+// after position n - 1 (0 for a whole sequence).  64 positions hold at most 32
+// stretches; each is kept in one word: start | len << 6 | min(alpha, len*c) << 13
+// (alpha >= len*c already flags the whole stretch; c <= 1024, so 17 bits).
+constexpr int SIR_RUNS = 32;
+// trailing one bits of x (64 when all are set; ctz of 0 is not defined)
+__device__ __forceinline__ int trailing_ones(uint64_t x) { return x == ~0ull ? 64 : __builtin_ctzll(~x); }
+
+__device__ __forceinline__ uint64_t sir_runs_lane(uint64_t bits, int n, int a, int c, const FastDiv& fc,
+                                                  int alpha0 = 0, int beta0 = 0) {
+  const uint64_t vm = lowmask(n);
+  bits &= vm;
+  const uint64_t z = ~bits & vm;
+  uint64_t out = bits;
+  uint32_t st[SIR_RUNS];
+  int K = 0, alpha = alpha0, pos = 0;
+  // no gaps, or nothing flagged anywhere near: nothing to add
+  bool more = z != 0 && (bits != 0 || alpha0 > 0 || beta0 > 0);
+#pragma unroll
+  for (int k = 0; k < SIR_RUNS; ++k) {
+    if (__ballot(more) == 0) break;
+    if (more) {
+      const uint64_t rest = z >> pos;
+      if (rest == 0) {
+        more = false;
+      } else {
+        const int m = __builtin_ctzll(rest);
+        alpha += m * a;
+        pos += m;
+        const int len = min(n - pos, trailing_ones(z >> pos));
+        st[k] = (uint32_t)pos | ((uint32_t)len << 6) | ((uint32_t)min(alpha, len * c) << 13);
+        const int P = min(len, (int)fc.div((uint32_t)alpha));
+        out |= lowmask(P) << pos;
+        alpha = max(0, alpha - len * c);
+        pos += len;
+        K = k + 1;
+        if (pos >= n) more = false;
+      }
+    }
+  }
+  int beta = beta0, nxt = n;
+#pragma unroll
+  for (int k = SIR_RUNS - 1; k >= 0; --k) {
+    if (__ballot(k < K) == 0) continue;
+    if (k < K) {
+      const int s0 = (int)(st[k] & 63u), len = (int)((st[k] >> 6) & 127u), al = (int)(st[k] >> 13);
+      const int e = s0 + len;
+      beta += (nxt - e) * a;
+      const int Q = min(len, (int)fc.div((uint32_t)beta));
+      out |= lowmask(Q) << (e - Q);
+      if (al + beta >= len * c) out |= lowmask(len) << s0;
+      beta = max(0, beta - len * c);
+      nxt = s0;
+    }
+  }
+  return out;
+}
+
+// A lane's effect on the best interval sums crossing it: an incoming alpha (best
+// sum of an interval ending just before the lane) leaves as max(Pf, alpha + Q),
+// an incoming beta (best sum starting just after it) as max(Pb, beta + Q), with
+// Q the lane's total weight, Pf its best suffix sum and Pb its best prefix sum
+// (both >= 0).  With W the running weight sum (W = 0 before the lane), Q is W at
+// the end, Pf = Q - min W and Pb = max W; the extremes are at run boundaries.
+__device__ __forceinline__ void sir_lane_maps(uint64_t bits, int n, int a, int c, int& Pf, int& Pb, int& Q) {
+  const uint64_t vm = lowmask(n);
+  const uint64_t z = ~bits & vm;
+  int W = 0, wmin = 0, wmax = 0, pos = 0;
+  while (pos < n) {
+    const uint64_t rest = z >> pos;
+    const int m = rest == 0 ? n - pos : min(n - pos, __builtin_ctzll(rest));   // flagged run
+    W += m * a;
+    wmax = max(wmax, W);
+    pos += m;
+    if (pos >= n) break;
+    const int len = min(n - pos, trailing_ones(z >> pos));                   // unflagged stretch (>= 1)
+    W -= len * c;
+    wmin = min(wmin, W);
+    pos += len;
+  }
+  Q = W;
+  Pf = W - wmin;
+  Pb = wmax;
+}
+
+// Exclusive scans of the lane maps along a group of G lanes: alpha_in from the
+// lanes before (composition in lane order), beta_in from the lanes after.
+__device__ __forceinline__ void sir_map_scans(int Pf, int Pb, int Q, int lig, int G, int& alpha_in, int& beta_in) {
+  // forward: composed map of lanes [0, lig] as (P, Q); apply to 0 -> P
+  int P = Pf, S = Q;
+  for (int d = 1; d < G; d <<= 1) {
+    const int Pp = __shfl_up(P, d, G), Sp = __shfl_up(S, d, G);
+    if (lig >= d) {
+      P = max(P, Pp + S);
+      S = Sp + S;
+    }
+  }
+  const int Pe = __shfl_up(P, 1, G);
+  alpha_in = lig == 0 ? 0 : max(0, Pe);
+  // backward: composed map of lanes [lig, G) in reverse order
+  P = Pb;
+  S = Q;
+  for (int d = 1; d < G; d <<= 1) {
+    const int Pn = __shfl_down(P, d, G), Sn = __shfl_down(S, d, G);
+    if (lig + d < G) {
+      P = max(P, Pn + S);
+      S = Sn + S;
+    }
+  }
+  const int Pn = __shfl_down(P, 1, G);
+  beta_in = lig == G - 1 ? 0 : max(0, Pn);
+}
+
 template <int L, class SM>
 __device__ __forceinline__ void phase_sir_time(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
   const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
@@ -1252,11 +1373,17 @@ __device__ __forceinline__ void phase_sir_time(const DevBlock& b, const DevParam
       const int nval = ok ? clampi(T - lig * L, 0, L) : 0;
       const uint64_t bits = ok ? (get_bits(rp, W, lig * L, L) & lowmask(nval)) : 0ull;
       const bool any = __ballot(bits != 0) != 0;
-      if (any || num >= den) {   // nothing flagged and eta < 1: nothing to add
-        const SirSum s = sir_lane_summary<L>(bits, nval, num, den);
-        int base, pmin, smax, gt, gn, gx;
-        sir_group_scan(s, lig, G, base, pmin, smax, gt, gn, gx);
-        const uint64_t out = sir_lane_apply<L>(bits, nval, num, den, base, pmin, smax);
+      if (num >= den) {   // eta = 1: every interval qualifies
+        write_row_bits<L>(rp, W, lowmask(nval), lig, G, ok);
+      } else if (any) {   // nothing flagged and eta < 1: nothing to add
+        // run by run, with the best interval sums entering from the
+        // neighbouring lanes of the row
+        const int a = num, c = den - num;
+        int Pf, Pb, Q, ain, bin;
+        sir_lane_maps(bits, nval, a, c, Pf, Pb, Q);
+        sir_map_scans(Pf, Pb, Q, lig, G, ain, bin);
+        const FastDiv fc((uint32_t)c);
+        const uint64_t out = sir_runs_lane(bits, nval, a, c, fc, ain, bin);
         write_row_bits<L>(rp, W, out, lig, G, ok);
       }
     }
@@ -1367,68 +1494,6 @@ __device__ __forceinline__ void phase_sir_freq_l(const DevBlock& b, const DevPar
   }
 }
 
-// SIR on one lane's whole sequence of n <= 64 positions (bit i = position i
-// flagged), run by run.  With weights a = num (flagged) and -c = num - den
-// (unflagged), a maximal stretch [s, e) of unflagged positions has alpha, the
-// best sum (>= 0) of an interval ending at s - 1, and beta, the best sum (>= 0)
-// of an interval starting at e; its position s + j is flagged iff some interval
-// through it sums to >= 0, i.e. iff j < floor(alpha/c), or j >= len - floor(beta/c),
-// or alpha + beta >= len*c.  alpha and beta follow the runs: m flagged positions
-// add m*a, a stretch of len positions takes x to max(0, x - len*c).  At most
-// SIR_RUNS stretches per lane; returns false (out untouched) when there are more.
-constexpr int SIR_RUNS = 16;
-__device__ __forceinline__ bool sir_runs_lane(uint64_t bits, int n, int a, int c, const FastDiv& fc,
-                                              uint64_t& out_bits) {
-  const uint64_t vm = lowmask(n);
-  bits &= vm;
-  const uint64_t z = ~bits & vm;
-  uint64_t out = bits;
-  uint32_t sl[SIR_RUNS];   // stretch start | length << 8
-  int al[SIR_RUNS];
-  int K = 0, alpha = 0, pos = 0;
-  bool more = bits != 0 && z != 0;   // no flags or no gaps: nothing to add
-#pragma unroll
-  for (int k = 0; k < SIR_RUNS; ++k) {
-    if (__ballot(more) == 0) break;
-    if (more) {
-      const uint64_t rest = z >> pos;
-      if (rest == 0) {
-        more = false;
-      } else {
-        const int m = __builtin_ctzll(rest);
-        alpha += m * a;
-        pos += m;
-        const int len = __builtin_ctzll(~(z >> pos));
-        sl[k] = (uint32_t)pos | ((uint32_t)len << 8);
-        al[k] = alpha;
-        const int P = min(len, (int)fc.div((uint32_t)alpha));
-        out |= lowmask(P) << pos;
-        alpha = max(0, alpha - len * c);
-        pos += len;
-        K = k + 1;
-        if (pos >= n) more = false;
-      }
-    }
-  }
-  if (more && (z >> pos) != 0) return false;
-  int beta = 0, nxt = n;
-#pragma unroll
-  for (int k = SIR_RUNS - 1; k >= 0; --k) {
-    if (__ballot(k < K) == 0) continue;
-    if (k < K) {
-      const int st = (int)(sl[k] & 255u), len = (int)(sl[k] >> 8), e = st + len;
-      beta += (nxt - e) * a;
-      const int Q = min(len, (int)fc.div((uint32_t)beta));
-      out |= lowmask(Q) << (e - Q);
-      if (al[k] + beta >= len * c) out |= lowmask(len) << st;
-      beta = max(0, beta - len * c);
-      nxt = st;
-    }
-  }
-  out_bits = out;
-  return true;
-}
-
 // flag bytes of one row word: nv (<= 64) samples from t0, bit j -> byte j
 __device__ __forceinline__ void write_word_bytes(const DevBlock& b, int row, int t0, int nv, uint64_t w) {
   GLB uint8_t* fp = gp<uint8_t>(b.flags) + (int64_t)row * b.fstride + t0;
@@ -1477,8 +1542,7 @@ __device__ __forceinline__ void phase_sir_freq_col(const DevBlock& b, const DevP
       out = ok ? lowmask(C) : 0ull;   // eta = 1: every interval qualifies
     } else {
       const FastDiv fc((uint32_t)(den - num));
-      if (!sir_runs_lane(bits, C, num, den - num, fc, out))
-        out = sir_lane_apply<64>(bits, C, num, den, 0, BIG, -BIG);
+      out = sir_runs_lane(bits, C, num, den - num, fc);
     }
     const uint64_t nb = ok ? (out & ~bits) : 0ull;
     if (__ballot(nb != 0) != 0) {
@@ -1730,6 +1794,11 @@ __device__ __forceinline__ void phase_write(const DevBlock& b, const DevParams& 
 // the packed integer form): 2 waves per SIMD, 256 VGPRs, no spills.  The float
 // frequency slab (81 KB of LDS) allows one workgroup per CU anyway.
 constexpr int float_waves_per_eu = 2;
+// SIR along time moves little data per work item and waits on dependent global
+// loads: more resident waves (6 per SIMD) pay more than the few spills they cost.
+#ifndef LOF_SIRT_WAVES_PER_EU
+#define LOF_SIRT_WAVES_PER_EU 6
+#endif
 
 // A kernel's work items are (block, chunk) pairs, item = block * maxch + chunk;
 // chunks past a smaller block's count return at once.  With counter == nullptr
@@ -1811,7 +1880,7 @@ __global__ __launch_bounds__(WG, INT ? LOF_WAVES_PER_EU : float_waves_per_eu) vo
 
 // Phase C: SIR operator along time (rows in chunks), then along frequency (slabs)
 template <int L>
-__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_sir_time_kernel(const DevBlock* __restrict__ blocks, int nb,
+__global__ __launch_bounds__(WG, LOF_SIRT_WAVES_PER_EU) void lof_sir_time_kernel(const DevBlock* __restrict__ blocks, int nb,
                                                                             int maxch, int* counter, DevParams P) {
   __shared__ SmSirT sm;
   run_items(nb * maxch, counter, [&](int it) __attribute__((always_inline)) {
