@@ -46,10 +46,12 @@ DEADLINE_S = T * (64.0 / 195.3125e3)   # 3072 samples of 327.68 us
 DOMINANT_KERNEL = {"stats": "lof_stats_kernel<true>", "sumthreshold_time": "lof_time_kernel<true, 48>",
                    "sumthreshold_freq": "lof_freq_kernel<true>", "sir_time": "lof_sir_time_kernel<48>",
                    "sir_freq": "lof_sir_freq_kernel", "history_write": "lof_final_kernel<true>"}
-# bytes each phase must move per sample: 2 B of complex int8 input, 1 bit of mask
-# per read or write, 1 flag byte (history ring traffic is below 3% and left out)
+# bytes each phase must move per sample here: 2 B of complex int8 input, 1 bit of
+# mask per read or write, 1 flag byte (written by the SIR frequency pass for
+# blocks of up to 64 channels); the history pass reads the mask (its reads of
+# flagged samples depend on the data, and the ring traffic is below 3%)
 DOMINANT_BYTES_PER_SAMPLE = {"stats": 2.0, "sumthreshold_time": 2.125, "sumthreshold_freq": 2.25,
-                             "sir_time": 0.25, "sir_freq": 0.25, "history_write": 3.125}
+                             "sir_time": 0.25, "sir_freq": 1.25, "history_write": 0.125}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_config1.txt")
 KERNEL_SOURCES = ("lof_device.hpp", "lof_kernels.hpp", "lof.hip")
 
