@@ -336,15 +336,17 @@ struct SmFreq {
   // integer slabs hold 64 columns per wave (one lane per column, up to 64
   // channels): 64 x 513 u16; float slabs the generic (G*32) x (NW*64/G + 1)
   static constexpr int TE = INT ? (64 * (NW * 64 + 1)) : (TILE_ELEMS + TILE_PAD);
+  // the threshold table first: its LDS address then fits the 16-bit offset field
+  // of ds_read, so a table read costs no address add
+  int32_t G[ST_MAX_LEVELS][128];
+  double T[16];
+  float Tf[16];
   union {
     struct {
       TileT t[TE];                 // frequency slab of powers (u16 values / float)
       uint64_t w[TILE_WORDS];      // mask words of the slab
     } f;
   } u;
-  double T[16];
-  float Tf[16];
-  int32_t G[ST_MAX_LEVELS][128];
 };
 
 struct SmSirT {

@@ -537,12 +537,24 @@ __device__ __forceinline__ uint64_t st_core(LD& ld, uint64_t fm, const int lig, 
 }
 
 // Integer input, prefix form.  A lane keeps the inclusive prefix sums
+// bit b of x as 0 or ~0 (v_bfe_i32).  Opaque, so that `v & bit_mask(x, b)` stays
+// one bit-field extract and one AND instead of a compare and a select.
+__device__ __forceinline__ uint32_t bit_mask(uint32_t x, int b) {
+  uint32_t k = (uint32_t)__builtin_amdgcn_sbfe((int)x, b, 1);
+  asm("" : "+v"(k));
+  return k;
+}
+
 // Y[i] = sum of v over the group's positions up to lig*L + i, modulo 2^32: every
 // true window word is below 2^30, so differences of prefixes are exact.  The
 // window of I starting at lane position i is Y(i+I-1) - Y(i-1); Y(j) for j >= L
 // comes from the next one or two lanes by DPP, Y(-1) is the prefix before the
-// lane (0 in the first lane of a group).  A level that changed the mask refills
-// v and recomputes the prefixes once, at a cost that does not grow with the level.
+// lane (0 in the first lane of a group).  A level that changed the mask rebuilds
+// the prefixes of each lane from its own samples only: the later lanes are not
+// told, so a lane's prefixes stay too large by what the lanes before it dropped.
+// Windows inside a lane do not see that offset; a window reaching into the next
+// lane subtracts E, the total this lane has dropped so far, and one reaching two
+// lanes ahead subtracts E + E(next lane).
 template <int L>
 __device__ __forceinline__ uint32_t px_get(const uint32_t (&Y)[L], int j) {
   if (j < L) return Y[j < L ? j : 0];
@@ -550,10 +562,14 @@ __device__ __forceinline__ uint32_t px_get(const uint32_t (&Y)[L], int j) {
   return shl1(shl1(Y[(j >= 2 * L && j < 3 * L) ? j - 2 * L : 0]));
 }
 
-template <int L>
-__device__ __forceinline__ uint32_t px_win(const uint32_t (&Y)[L], uint32_t yprev, int i, int I) {
+// CORR: the wave has dropped samples, so windows crossing lanes take e1 / e2
+template <int L, bool CORR>
+__device__ __forceinline__ uint32_t px_win(const uint32_t (&Y)[L], uint32_t yprev, int i, int I, uint32_t e1,
+                                           uint32_t e2) {
   const uint32_t lo = (i == 0) ? yprev : Y[(i > 0) ? i - 1 : 0];
-  return px_get<L>(Y, i + I - 1) - lo;
+  const int j = i + I - 1;
+  if (!CORR || j < L) return px_get<L>(Y, j) - lo;
+  return px_get<L>(Y, j) - (lo + (j < 2 * L ? e1 : e2));
 }
 
 // v under mask fm -> prefixes; returns Y(-1)
@@ -586,41 +602,36 @@ __device__ __forceinline__ uint32_t px_fill(LD& ld, uint64_t fm, uint32_t (&Y)[L
 }
 
 // Remove the samples of `drop` (newly flagged positions of the lane) from the
-// prefixes: a sample's packed value is Y[i] - Y[i-1], and every later prefix of
-// the group loses the sum of dropped values before it.
+// lane's prefixes: a sample's packed value is Y[i] - Y[i-1], and the prefixes are
+// re-accumulated from yprev over the kept samples.  E grows by what the lane lost.
 template <int L>
-__device__ __forceinline__ void px_drop(uint32_t (&Y)[L], uint32_t& yprev, uint64_t drop, int lig, int G) {
-  const uint32_t dlo = (uint32_t)drop, dhi = (uint32_t)(drop >> 32);
-  uint32_t run = 0, prev = yprev;
+__device__ __forceinline__ void px_drop(uint32_t (&Y)[L], const uint32_t yprev, uint64_t drop, uint32_t& E) {
+  const uint32_t klo = ~(uint32_t)drop, khi = ~(uint32_t)(drop >> 32);
+  const uint32_t old_end = Y[L - 1];
+  // sample values first, last to first, then the kept ones re-accumulated: both
+  // steps overwrite Y[i] in place (no register rotation)
+#pragma unroll
+  for (int i = L - 1; i >= 0; --i) Y[i] -= (i > 0) ? Y[(i > 0) ? i - 1 : 0] : yprev;
+  uint32_t acc = yprev;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    const uint32_t y = Y[i];
-    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)(i < 32 ? dlo : dhi), i & 31, 1);   // 0 or ~0
-    run += (y - prev) & m;
-    prev = y;
-    Y[i] = y - run;
+    acc += Y[i] & bit_mask((i < 32 ? klo : khi), i & 31);
+    Y[i] = acc;
   }
-  uint32_t incl = run;
-  for (int d = 1; d < G; d <<= 1) {
-    const uint32_t t = __shfl_up(incl, d, G);
-    if (lig >= d) incl += t;
-  }
-  const uint32_t off = incl - run;
-#pragma unroll
-  for (int i = 0; i < L; ++i) Y[i] -= off;
-  yprev -= off;
+  E += old_end - acc;
 }
 
 // Window bits are assembled most significant first: acc = (acc << 1) | sign(g - d),
 // one v_alignbit per window.  For every full window d <= 2^30 and
 // -2^30 < g < 2^31, so g - d does not overflow and its sign is (d > g).
-// The empty asm pins d: without it the compiler folds g into the window
-// difference, (g + Y[i-1]) - dpp(Y[j]), and that combined DPP subtract gave
-// wrong lane-crossing windows on gfx950 while the plain form, dpp(Y[j]) - Y[i-1],
-// is exact.
+// g - d is an opaque subtract: left to the compiler, g is folded into the window
+// difference, (g + Y[i-1]) - dpp(Y[j]), and that combined DPP subtract gave wrong
+// lane-crossing windows on gfx950 while the plain form, dpp(Y[j]) - Y[i-1], is
+// exact.  (An empty asm on d has the same effect but costs a copy of d.)
 __device__ __forceinline__ uint32_t push_bit(uint32_t acc, int32_t g, uint32_t d) {
-  asm("" : "+v"(d));
-  return __builtin_amdgcn_alignbit(acc, (uint32_t)(g - (int32_t)d), 31);
+  uint32_t t;
+  asm("v_sub_u32 %0, %1, %2" : "=v"(t) : "v"(g), "v"(d));
+  return __builtin_amdgcn_alignbit(acc, t, 31);
 }
 
 #ifndef LOF_PXB
@@ -629,12 +640,12 @@ __device__ __forceinline__ uint32_t push_bit(uint32_t acc, int32_t g, uint32_t d
 constexpr int PXB = LOF_PXB;   // windows per batch of table reads
 
 template <int L, int K, class SM>
-__device__ __forceinline__ void st_level_px(uint32_t (&Y)[L], uint32_t& yprev, uint64_t& fm, uint64_t& pend,
-                                            const int lig, const int G, const int n, const int pos0,
+__device__ __forceinline__ void st_level_px(uint32_t (&Y)[L], const uint32_t yprev, uint32_t& E, uint64_t& fm,
+                                            uint64_t& pend, const int lig, const int n, const int pos0,
                                             const uint64_t vmask, const SM& sm) {
   constexpr int I = 1 << K;
   static_assert(I <= 2 * L && L % PXB == 0, "a window may reach at most two lanes ahead");
-  if (__ballot(pend != 0) != 0) px_drop<L>(Y, yprev, pend, lig, G);
+  if (__ballot(pend != 0) != 0) px_drop<L>(Y, yprev, pend, E);
   pend = 0;
   const int nvw = n - I + 1 - pos0;
   const int32_t* Gk = sm.G[K];
@@ -644,19 +655,20 @@ __device__ __forceinline__ void st_level_px(uint32_t (&Y)[L], uint32_t& yprev, u
     const int32_t g = Gk[I];
 #pragma unroll
     for (int i = L - 1; i >= 0; --i) {
-      const uint32_t d = px_win<L>(Y, yprev, i, I);
+      const uint32_t d = px_win<L, false>(Y, yprev, i, I, 0u, 0u);
       if (i >= 32) hi = push_bit(hi, g, d); else lo = push_bit(lo, g, d);
       if (i % PXB == 0) __builtin_amdgcn_sched_barrier(0);
     }
   } else {
     // PXB windows at a time: their table reads in flight before they are used
+    const uint32_t e1 = E, e2 = (I + L - 1 > 2 * L) ? E + shl1(E) : E;
 #pragma unroll
     for (int i0 = L - PXB; i0 >= 0; i0 -= PXB) {
       uint32_t d[PXB];
       int32_t g[PXB];
 #pragma unroll
       for (int j = 0; j < PXB; ++j) {
-        d[j] = px_win<L>(Y, yprev, i0 + j, I);
+        d[j] = px_win<L, true>(Y, yprev, i0 + j, I, e1, e2);
         g[j] = Gk[(d[j] >> 2) & 127u];
       }
 #pragma unroll
@@ -697,8 +709,9 @@ __device__ __forceinline__ uint64_t st_core_px(LD& ld, uint64_t fm, const int li
     if (ld.ok && lig == 0) *row_sum = rs;
   }
   uint64_t pend = 0;
+  uint32_t E = 0;
 #define LOF_PLEVEL(K) \
-  if (K < kend) st_level_px<L, K>(Y, yprev, fm, pend, lig, G, n, pos0, vmask, sm);
+  if (K < kend) st_level_px<L, K>(Y, yprev, E, fm, pend, lig, n, pos0, vmask, sm);
   LOF_PLEVEL(0)
   LOF_PLEVEL(1)
   LOF_PLEVEL(2)
@@ -1030,15 +1043,14 @@ __device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, int lane) {
 // store per channel word.
 template <int NC>
 __device__ __forceinline__ void col_drop(uint32_t (&Q)[NC], uint64_t drop) {
-  const uint32_t dlo = (uint32_t)drop, dhi = (uint32_t)(drop >> 32);
-  uint32_t run = 0, prev = 0;
+  const uint32_t klo = ~(uint32_t)drop, khi = ~(uint32_t)(drop >> 32);
+#pragma unroll
+  for (int i = NC - 1; i > 0; --i) Q[i] -= Q[i - 1];
+  uint32_t acc = 0;
 #pragma unroll
   for (int i = 0; i < NC; ++i) {
-    const uint32_t y = Q[i];
-    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)(i < 32 ? dlo : dhi), i & 31, 1);
-    run += (y - prev) & m;
-    prev = y;
-    Q[i] = y - run;
+    acc += Q[i] & bit_mask((i < 32 ? klo : khi), i & 31);
+    Q[i] = acc;
   }
 }
 
