@@ -339,7 +339,10 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
 
 // Thresholds of a block from its BlockState into shared memory.  Integer input
 // also gets exact window thresholds: flag iff S > floor(c * T_k), stored packed
-// against the window word D = S*512 + 4c as G = floor(c*T_k)*512 + 511.
+// against the window word D = S*256 + 4c as G = floor(c*T_k)*256 + 4c + 255,
+// indexed by the low bits (D >> 2) & 63.  Count 64 and count 0 share index 0: a
+// window with no unflagged sample has D = 0, so that entry is max(G_64, 0), which
+// D = 0 never exceeds and every 64-sample window with G_64 < 0 does.
 template <bool INT, class SM>
 __device__ __forceinline__ void load_thresholds(const DevBlock& b, const DevParams& P, SM& sm) {
   const int tid = thread_id();
@@ -352,18 +355,20 @@ __device__ __forceinline__ void load_thresholds(const DevBlock& b, const DevPara
   __syncthreads();
   if (INT) {
     for (int i = tid; i < ST_MAX_LEVELS * 128; i += WG) {
-      const int k = i >> 7, c = i & 127;
+      const int k = i >> 7, idx = i & 127;
+      const int c = idx == 0 ? 64 : idx;
       const double T = sm.T[k];
       const double cd = (double)c;
       const double prod = cd * T;
       const double err = __builtin_fma(cd, T, -prod);
       double fl = __builtin_floor(prod);
       if (prod == fl && err < 0.0) fl -= 1.0;
+      // S lies in [0, 2^21]: a floor at or above 2^21 never flags, one below 0 always
       int32_t g;
-      if (fl >= 4194303.0) g = 0x7fffffff;
-      else if (fl < -2097152.0) g = -2097152 * 512 + 511;
-      else g = (int32_t)fl * 512 + 511;
-      sm.G[k][c] = g;
+      if (fl >= 2097152.0) g = 0x7fffffff;
+      else g = (int32_t)__builtin_fmax(fl, -1.0) * 256 + 4 * c + 255;
+      if (idx == 0) g = g > 0 ? g : 0;
+      sm.G[k][idx] = g;
     }
     __syncthreads();
   }
@@ -376,8 +381,8 @@ __device__ __forceinline__ void load_thresholds(const DevBlock& b, const DevPara
 // are left out of the window's sum and count; a window whose unflagged mean
 // exceeds T_k flags all its samples.  Only full windows (s + I <= n) are judged.
 //
-// Integer input: v = p*512 + 4 for an unflagged sample, 0 for a flagged one, so a
-// window word D = S*512 + 4c packs the exact unflagged sum S and count c; the test
+// Integer input: v = p*256 + 4 for an unflagged sample, 0 for a flagged one, so a
+// window word D = S*256 + 4c packs the exact unflagged sum S and count c; the test
 // S > floor(c*T_k) is D > G_k[c].  Float input: float32 sums and counts, test
 // S > c*T_k in float32.  Window sums of level k are D_k(s) = D_{k-1}(s) +
 // D_{k-1}(s + I/2); after a level that changed the mask they are rebuilt from v.
@@ -466,14 +471,14 @@ __device__ __forceinline__ void st_level(LD& ld, typename PowT<INT>::T (&D)[L], 
 #pragma unroll
         for (int i = 0; i < L; ++i) {
           const uint32_t d = (uint32_t)D[i];
-          any |= __ballot((int32_t)d > Gk[(d >> 2) & 127u]);
+          any |= __ballot((int32_t)d > Gk[(d >> 2) & 63u]);
           if ((i & 15) == 15) __builtin_amdgcn_sched_barrier(0);   // bound the hoisted table reads
         }
         if (any) {
 #pragma unroll
           for (int i = 0; i < L; ++i) {
             const uint32_t d = (uint32_t)D[i];
-            const uint32_t h = ((int32_t)d > Gk[(d >> 2) & 127u]) ? 1u : 0u;
+            const uint32_t h = ((int32_t)d > Gk[(d >> 2) & 63u]) ? 1u : 0u;
             if (i < 32) lo |= h << i; else hi |= h << (i - 32);
             if ((i & 15) == 15) __builtin_amdgcn_sched_barrier(0);
           }
@@ -537,12 +542,27 @@ __device__ __forceinline__ uint64_t st_core(LD& ld, uint64_t fm, const int lig, 
 }
 
 // Integer input, prefix form.  A lane keeps the inclusive prefix sums
-// bit b of x as 0 or ~0 (v_bfe_i32).  Opaque, so that `v & bit_mask(x, b)` stays
-// one bit-field extract and one AND instead of a compare and a select.
-__device__ __forceinline__ uint32_t bit_mask(uint32_t x, int b) {
-  uint32_t k = (uint32_t)__builtin_amdgcn_sbfe((int)x, b, 1);
+// bit b of x as 0 or 1 (v_bfe_u32).  Opaque, so that `acc + __umul24(bit01(x, b), v)`
+// stays one bit-field extract and one v_mad_u32_u24 instead of a compare and a
+// select.  A packed sample value is below 2^24 (p <= 2^15), as the 24-bit multiply
+// needs.
+__device__ __forceinline__ uint32_t bit01(uint32_t x, int b) {
+  uint32_t k = __builtin_amdgcn_ubfe(x, b, 1);
   asm("" : "+v"(k));
   return k;
+}
+
+// Window bits are assembled most significant first: acc = (acc << 1) | sign(g - d),
+// one v_alignbit per window.  For every full window d <= 2^30 and
+// -2^30 < g < 2^31, so g - d does not overflow and its sign is (d > g).
+// g - d is an opaque subtract: left to the compiler, g is folded into the window
+// difference, (g + Y[i-1]) - dpp(Y[j]), and that combined DPP subtract gave wrong
+// lane-crossing windows on gfx950 while the plain form, dpp(Y[j]) - Y[i-1], is
+// exact.  (An empty asm on d has the same effect but costs a copy of d.)
+__device__ __forceinline__ uint32_t push_bit(uint32_t acc, int32_t g, uint32_t d) {
+  uint32_t t;
+  asm("v_sub_u32 %0, %1, %2" : "=v"(t) : "v"(g), "v"(d));
+  return __builtin_amdgcn_alignbit(acc, t, 31);
 }
 
 // Y[i] = sum of v over the group's positions up to lig*L + i, modulo 2^32: every
@@ -573,11 +593,19 @@ __device__ __forceinline__ uint32_t px_win(const uint32_t (&Y)[L], uint32_t ypre
 }
 
 // v under mask fm -> prefixes; returns Y(-1)
+// The rows start with nothing flagged, so level 0 (windows of one sample, count 1)
+// is tested on the loaded values themselves: w0 gets bit i iff v_i > g0.
 template <int L, class LD>
-__device__ __forceinline__ uint32_t px_fill(LD& ld, uint64_t fm, uint32_t (&Y)[L], int lig, int G,
-                                            uint32_t& lane_total) {
+__device__ __forceinline__ uint32_t px_fill(LD& ld, uint32_t (&Y)[L], int lig, int G, uint32_t& lane_total,
+                                            const int32_t g0, uint64_t& w0) {
   float unused[L];
-  ld.fill(fm, Y, unused);
+  ld.fill(0ull, Y, unused);
+  uint32_t lo = 0, hi = 0;
+#pragma unroll
+  for (int i = L - 1; i >= 0; --i) {
+    if (i >= 32) hi = push_bit(hi, g0, Y[i]); else lo = push_bit(lo, g0, Y[i]);
+  }
+  w0 = (uint64_t)lo | ((uint64_t)hi << 32);
   uint32_t run = 0;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
@@ -615,23 +643,10 @@ __device__ __forceinline__ void px_drop(uint32_t (&Y)[L], const uint32_t yprev, 
   uint32_t acc = yprev;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    acc += Y[i] & bit_mask((i < 32 ? klo : khi), i & 31);
+    acc += __umul24(bit01((i < 32 ? klo : khi), i & 31), Y[i]);   // one v_mad_u32_u24
     Y[i] = acc;
   }
   E += old_end - acc;
-}
-
-// Window bits are assembled most significant first: acc = (acc << 1) | sign(g - d),
-// one v_alignbit per window.  For every full window d <= 2^30 and
-// -2^30 < g < 2^31, so g - d does not overflow and its sign is (d > g).
-// g - d is an opaque subtract: left to the compiler, g is folded into the window
-// difference, (g + Y[i-1]) - dpp(Y[j]), and that combined DPP subtract gave wrong
-// lane-crossing windows on gfx950 while the plain form, dpp(Y[j]) - Y[i-1], is
-// exact.  (An empty asm on d has the same effect but costs a copy of d.)
-__device__ __forceinline__ uint32_t push_bit(uint32_t acc, int32_t g, uint32_t d) {
-  uint32_t t;
-  asm("v_sub_u32 %0, %1, %2" : "=v"(t) : "v"(g), "v"(d));
-  return __builtin_amdgcn_alignbit(acc, t, 31);
 }
 
 #ifndef LOF_PXB
@@ -669,7 +684,7 @@ __device__ __forceinline__ void st_level_px(uint32_t (&Y)[L], const uint32_t ypr
 #pragma unroll
       for (int j = 0; j < PXB; ++j) {
         d[j] = px_win<L, true>(Y, yprev, i0 + j, I, e1, e2);
-        g[j] = Gk[(d[j] >> 2) & 127u];
+        g[j] = Gk[(d[j] >> 2) & 63u];
       }
 #pragma unroll
       for (int j = PXB - 1; j >= 0; --j) {
@@ -687,20 +702,21 @@ __device__ __forceinline__ void st_level_px(uint32_t (&Y)[L], const uint32_t ypr
 }
 
 // psum: the power sum of the lane's samples (the first fill runs with no flags:
-// its lane total is 512 * sum(p) + 4 * nval, exactly, below 2^31)
+// its lane total is 256 * sum(p) + 4 * nval, exactly, below 2^30)
 template <int L, class LD, class SM>
-__device__ __forceinline__ uint64_t st_core_px(LD& ld, uint64_t fm, const int lig, const int G, const int n,
-                                               const int nlev, const SM& sm, uint32_t& psum,
-                                               GLB uint64_t* row_sum = nullptr) {
+__device__ __forceinline__ uint64_t st_core_px(LD& ld, const int lig, const int G, const int n, const int nlev,
+                                               const SM& sm, uint32_t& psum, GLB uint64_t* row_sum = nullptr) {
   uint32_t Y[L];
+  uint64_t fm = 0;
   const int pos0 = lig * L;
   const int nval = clampi(n - pos0, 0, L);
   const uint64_t vmask = lowmask(nval);
   int kend = 0;
   while (kend < nlev && (1 << kend) <= n) ++kend;   // levels with I <= n
   uint32_t lane_total;
-  uint32_t yprev = px_fill<L>(ld, fm, Y, lig, G, lane_total);
-  psum = (lane_total - 4u * (uint32_t)nval) >> 9;
+  uint64_t w0;
+  const uint32_t yprev = px_fill<L>(ld, Y, lig, G, lane_total, sm.G[0][1], w0);
+  psum = (lane_total - 4u * (uint32_t)nval) >> 8;
   if (row_sum != nullptr) {
     // the row's power sum (exact) for the history flagger, stored now so that
     // nothing extra stays live through the levels
@@ -710,9 +726,13 @@ __device__ __forceinline__ uint64_t st_core_px(LD& ld, uint64_t fm, const int li
   }
   uint64_t pend = 0;
   uint32_t E = 0;
+  if (kend > 0) {
+    // level 0: every valid position is a full window; a window flags only itself
+    fm = w0 & vmask;
+    pend = fm;
+  }
 #define LOF_PLEVEL(K) \
   if (K < kend) st_level_px<L, K>(Y, yprev, E, fm, pend, lig, n, pos0, vmask, sm);
-  LOF_PLEVEL(0)
   LOF_PLEVEL(1)
   LOF_PLEVEL(2)
   LOF_PLEVEL(3)
@@ -748,15 +768,15 @@ struct TimeLoader {
           for (int m = 0; m < 4; ++m) {
             const int i0 = 8 * j + 2 * m;
             const uint32_t p0 = ci8_power(a[m] & 0xffffu), p1 = ci8_power(a[m] >> 16);
-            D[i0] = ((fm >> i0) & 1ull) ? 0u : p0 * 512u + 4u;
-            D[i0 + 1] = ((fm >> (i0 + 1)) & 1ull) ? 0u : p1 * 512u + 4u;
+            D[i0] = ((fm >> i0) & 1ull) ? 0u : p0 * 256u + 4u;
+            D[i0 + 1] = ((fm >> (i0 + 1)) & 1ull) ? 0u : p1 * 256u + 4u;
           }
         }
       } else {
 #pragma unroll
         for (int i = 0; i < L; ++i) {
           const bool live = ok && i < nval && !((fm >> i) & 1ull);
-          D[i] = live ? ci8_power(*(const GLB uint16_t*)(rb + 2 * i)) * 512u + 4u : 0u;
+          D[i] = live ? ci8_power(*(const GLB uint16_t*)(rb + 2 * i)) * 256u + 4u : 0u;
         }
       }
     } else {
@@ -818,7 +838,7 @@ struct TileLoader {
       const bool live = valid && !((fm >> i) & 1ull);
       if (INT) {
         const uint32_t p = valid ? (uint32_t)tile[(ch0 + i) * stride + col] : 0u;
-        D[i] = (typename PowT<INT>::T)(live ? p * 512u + 4u : 0u);
+        D[i] = (typename PowT<INT>::T)(live ? p * 256u + 4u : 0u);
       } else {
         const float p = valid ? (float)tile[(ch0 + i) * stride + col] : 0.0f;
         D[i] = (typename PowT<INT>::T)(live ? p : 0.0f);
@@ -888,12 +908,16 @@ __device__ __forceinline__ void phase_time(const DevBlock& b, const DevParams& P
       uint64_t fm;
       if constexpr (INT) {
         uint32_t psum;
-        fm = st_core_px<L>(ld, 0ull, lig, G, T, nlev, sm, psum,
+        fm = st_core_px<L>(ld, lig, G, T, nlev, sm, psum,
                            gp<uint64_t>(P.rowsum) + (int64_t)b.sidx * P.maxC + (ok ? row : 0));
       } else {
         fm = st_core<INT, L>(ld, 0ull, lig, T, 0, nlev, sm);
       }
-      write_row_bits<L>(m0 + (int64_t)(ok ? row : 0) * W, W, fm, lig, G, ok);
+      // the row index again from the thread id: holding it through the levels
+      // would take registers the levels need
+      const int t2 = thread_id();
+      const int row2 = chunk * NW * R + (t2 >> 6) * R + (t2 & 63) / G;
+      write_row_bits<L>(m0 + (int64_t)(ok ? row2 : 0) * W, W, fm, lig, G, ok);
     }
   } else if constexpr (L == 64) {
     // long rows (only laid out with L == 64): segments of 64*L positions,
@@ -911,7 +935,7 @@ __device__ __forceinline__ void phase_time(const DevBlock& b, const DevParams& P
         const bool core = pos >= c0 && pos < c1;
         if constexpr (INT) {
           uint32_t psum;
-          fm = st_core_px<L>(ld, 0ull, lane, 64, n, nlev, sm, psum);
+          fm = st_core_px<L>(ld, lane, 64, n, nlev, sm, psum);
           if (!core) psum = 0;
           for (int d = 32; d >= 1; d >>= 1) psum += __shfl_xor(psum, d);   // < 2^27 per segment
           rsum += psum;
@@ -1049,7 +1073,7 @@ __device__ __forceinline__ void col_drop(uint32_t (&Q)[NC], uint64_t drop) {
   uint32_t acc = 0;
 #pragma unroll
   for (int i = 0; i < NC; ++i) {
-    acc += Q[i] & bit_mask((i < 32 ? klo : khi), i & 31);
+    acc += __umul24(bit01((i < 32 ? klo : khi), i & 31), Q[i]);
     Q[i] = acc;
   }
 }
@@ -1080,7 +1104,7 @@ __device__ __forceinline__ void col_level_px(uint32_t (&Q)[NC], uint64_t& fm, ui
       for (int j = 0; j < PXB; ++j) {
         if (i0 + j < NWIN) {
           d[j] = col_win<NC>(Q, i0 + j, I);
-          g[j] = Gk[(d[j] >> 2) & 127u];
+          g[j] = Gk[(d[j] >> 2) & 63u];
         }
       }
 #pragma unroll
@@ -1129,7 +1153,7 @@ __device__ __forceinline__ void phase_freq_col(const DevBlock& b, const DevParam
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int i = i0 + j;
-      const uint32_t v = (ok && !((fm >> i) & 1ull)) ? ci8_power(w[j]) * 512u + 4u : 0u;
+      const uint32_t v = (ok && !((fm >> i) & 1ull)) ? ci8_power(w[j]) * 256u + 4u : 0u;
       run += v;
       Q[i] = run;
       asm("" : "+v"(Q[i]));   // opaque: the loaded values need not stay alive

@@ -71,6 +71,28 @@ def test_ci8_degenerate(lof, variant):
     assert st[0]["median"] == r.median and st[0]["stddev"] == r.stddev
 
 
+@pytest.mark.parametrize("sens", [-1.0, 0.0, 1e-3, 0.3, 40.0, 1e12])
+def test_ci8_threshold_extremes(sens):
+    """Thresholds below zero, at the median and above any window sum: the clamps of
+    the packed window-threshold table and its entry shared by counts 0 and 64."""
+    import torch  # noqa: F401
+    import paper_1701_08197_amd as P
+    say(f"[ci8_threshold_extremes] sensitivity={sens}")
+    fl = P.Flagger(P.default_params(max_streams=8, max_channels=64, max_blocks_per_call=4,
+                                    max_samples_per_call=1 << 20, sensitivity=sens))
+    try:
+        items = [(ci8_case(321, 64, 3072), O.CI8, -1), (ci8_case(322, 16, 300), O.CI8, -1),
+                 (np.full((8, 200, 2), -128, dtype=np.int8), O.CI8, -1)]   # p = 2^15 everywhere, sigma 0
+        flags, st = run_gpu(fl, items)
+        prm = oracle_params(fl.params)
+        for (x, _, _), f, s in zip(items, flags, st):
+            r = O.flag_block(x, O.CI8, prm)
+            assert mismatch(f, r.flags) == 0
+            assert s["threshold"][:7] == r.thresholds[:7]
+    finally:
+        fl.close()
+
+
 def test_ci8_batch_mixed_shapes(lof):
     say("[ci8_batch_mixed_shapes]")
     shapes = [(64, 3072), (16, 768), (3, 5000), (256, 100), (1, 1), (64, 4096), (40, 2100)]
