@@ -209,9 +209,8 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
     for (int j = 0; j < 8; ++j) {
       if (j < nv) {
         if (INT) {
+          // the exact histogram also yields sum(p) and sum(p^2) afterwards
           const uint32_t p = (uint32_t)v[j];
-          s1u += p;
-          s2u += (unsigned long long)(p * p);     // p <= 32768: p*p < 2^31
           atomicAdd(&sm.u.ihist[p >> 1], (p & 1u) ? 0x10000u : 1u);
         } else {
           const double d = (double)v[j];
@@ -247,6 +246,50 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
       consume(v, nv);
     }
   }
+  const uint32_t r0 = (uint32_t)((N - 1) / 2), r1 = (uint32_t)(N / 2);
+  bool hist_ok = false;
+  if (INT) {
+    __syncthreads();   // every wave's histogram increments done
+    // the 16-bit fields sum to N exactly when no counter wrapped; then bin p with
+    // count c adds c*p and c*p^2 to the exact sums
+    uint32_t s = 0;
+    for (int i = tid; i < IHIST_WORDS; i += WG) {
+      const uint32_t w = sm.u.ihist[i];
+      const uint32_t c0 = w & 0xffffu, c1 = w >> 16;
+      const uint32_t p0 = 2u * (uint32_t)i, p1 = p0 + 1u;
+      s += c0 + c1;
+      s1u += (unsigned long long)(c0 * p0 + c1 * p1);   // c <= 2^16 - 1, p0 + p1 < 2^16: below 2^32
+      s2u += (unsigned long long)c0 * (p0 * p0) + (unsigned long long)c1 * (p1 * p1);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+    if (lane == 0) sm.scan[wv] = s;
+    __syncthreads();
+    uint32_t tot = 0;
+    for (int w = 0; w < NW; ++w) tot += sm.scan[w];
+    __syncthreads();
+    hist_ok = tot == (uint32_t)N;
+    if (!hist_ok) {
+      // a counter wrapped (some power value occurs 2^16 times or more): the sums
+      // from the samples themselves
+      s1u = 0;
+      s2u = 0;
+      for (uint32_t it = tid; it < items; it += WG) {
+        const int row = (int)fd.div(it);
+        const int t0 = (int)(it - (uint32_t)row * (uint32_t)nch) * 8;
+        VT v[8];
+        const int nv = load8<INT>(b, row, t0, v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          if (j < nv) {
+            const uint32_t p = (uint32_t)v[j];
+            s1u += p;
+            s2u += (unsigned long long)(p * p);     // p <= 32768: p*p <= 2^30
+          }
+        }
+      }
+    }
+  }
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
     s1u += __shfl_xor(s1u, d);
@@ -262,30 +305,12 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
   }
   __syncthreads();
 
-  const uint32_t r0 = (uint32_t)((N - 1) / 2), r1 = (uint32_t)(N / 2);
   uint32_t k0, k1;
-  if (INT) {
-    // the 16-bit fields sum to N exactly when no counter wrapped
-    uint32_t s = 0;
-    for (int i = tid; i < IHIST_WORDS; i += WG) {
-      const uint32_t w = sm.u.ihist[i];
-      s += (w & 0xffffu) + (w >> 16);
-    }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
-    if (lane == 0) sm.scan[wv] = s;
-    __syncthreads();
-    uint32_t tot = 0;
-    for (int w = 0; w < NW; ++w) tot += sm.scan[w];
-    __syncthreads();
-    if (tot == (uint32_t)N) {
-      k0 = find_bin16(sm.u.ihist, r0, sm);
-      k1 = (r1 == r0) ? k0 : find_bin16(sm.u.ihist, r1, sm);
-    } else {
-      radix_select<INT>(b, sm, r0, r1, false, k0, k1);
-    }
+  if (INT && hist_ok) {
+    k0 = find_bin16(sm.u.ihist, r0, sm);
+    k1 = (r1 == r0) ? k0 : find_bin16(sm.u.ihist, r1, sm);
   } else {
-    radix_select<INT>(b, sm, r0, r1, true, k0, k1);
+    radix_select<INT>(b, sm, r0, r1, !INT, k0, k1);
   }
 
   if (tid == 0) {

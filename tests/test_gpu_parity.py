@@ -71,6 +71,27 @@ def test_ci8_degenerate(lof, variant):
     assert st[0]["median"] == r.median and st[0]["stddev"] == r.stddev
 
 
+@pytest.mark.parametrize("variant", ["const", "ternary", "mostly_zero"])
+def test_ci8_histogram_wrap(lof, variant):
+    """Blocks where one power value occurs 2^16 times or more: the packed 16-bit
+    histogram counters wrap, so the median comes from the radix select and the
+    power sums from the samples."""
+    say(f"[ci8_histogram_wrap] {variant}")
+    C, T = 64, 3072
+    rng = np.random.default_rng(4242)
+    if variant == "const":
+        x = np.full((C, T, 2), 5, dtype=np.int8)
+    elif variant == "ternary":
+        x = rng.integers(-1, 2, size=(C, T, 2)).astype(np.int8)
+    else:
+        x = np.zeros((C, T, 2), dtype=np.int8)
+        x[:, ::7, 0] = rng.integers(-128, 128, size=(C, len(range(0, T, 7)))).astype(np.int8)
+    flags, st = run_gpu(lof, [(x, O.CI8, -1)])
+    r = O.flag_block(x, O.CI8, oracle_params(lof.params))
+    assert st[0]["median"] == r.median and st[0]["stddev"] == r.stddev
+    assert mismatch(flags[0], r.flags) == 0
+
+
 @pytest.mark.parametrize("sens", [-1.0, 0.0, 1e-3, 0.3, 40.0, 1e12])
 def test_ci8_threshold_extremes(sens):
     """Thresholds below zero, at the median and above any window sum: the clamps of
