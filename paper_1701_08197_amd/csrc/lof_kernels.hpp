@@ -1637,8 +1637,8 @@ __device__ __forceinline__ void phase_sir_freq(const DevBlock& b, const DevParam
 // depend on this block, so its loads are issued first and overlap the loads of
 // the row's mask and samples.
 template <bool INT>
-__device__ __forceinline__ void row_unflagged(const DevBlock& b, const DevParams& P, int row, int lane, double& usum,
-                                              int& cnt) {
+__device__ __forceinline__ void row_unflagged(const DevBlock& b, const DevParams& P, int row, int lane,
+                                              uint64_t rowsum, double& usum, int& cnt) {
   const int T = b.T;
   const int W = (T + 63) >> 6;
   const GLB uint64_t* mrow = gp<uint64_t>(P.maskw) + b.mask_off + (int64_t)row * W;
@@ -1682,8 +1682,7 @@ __device__ __forceinline__ void row_unflagged(const DevBlock& b, const DevParams
       sfl += __shfl_xor(sfl, d);
       nf += __shfl_xor(nf, d);
     }
-    const uint64_t tot = gp<const uint64_t>(P.rowsum)[(int64_t)b.sidx * P.maxC + row];
-    usum = (double)(tot - sfl);   // integer sums < 2^53: exact
+    usum = (double)(rowsum - sfl);   // integer sums < 2^53: exact
     cnt = T - nf;
   } else {
     const int nch = (T + 7) >> 3;
@@ -1725,17 +1724,24 @@ __device__ __forceinline__ void phase_history(const DevBlock& b, const DevParams
   const int row = r0 + wv;   // one row per wave (a chunk is NW rows)
   if (s >= 0 && row < r1) {
     const int64_t idx = (int64_t)s * P.maxC + row;
+    // every load that does not depend on another is issued first: count, head,
+    // the ring in storage order (lane j reads slot j) and the row's power sum
     const int L = gp<const int32_t>(P.rcount)[idx];
     const int head = gp<const int32_t>(P.rhead)[idx];
     const GLB double* ring = gp<const double>(P.ring) + idx * P.H;
+    const bool small_ring = P.H <= 64;
+    const double xs = (small_ring && lane < P.H) ? ring[lane] : 0.0;
+    const uint64_t rowsum = INT ? gp<const uint64_t>(P.rowsum)[(int64_t)b.sidx * P.maxC + row] : 0ull;
+    double usum;
+    int cnt;
+    row_unflagged<INT>(b, P, row, lane, rowsum, usum, cnt);
     const bool judge = L >= P.Hmin;
     // the first 64 entries in ring order, oldest first (lane j holds entry j)
     int k0 = head - L + lane;
     if (k0 < 0) k0 += P.H;
-    const double x0 = (judge && lane < L) ? ring[k0] : 0.0;
-    double usum;
-    int cnt;
-    row_unflagged<INT>(b, P, row, lane, usum, cnt);
+    const int ks = (lane < L) ? k0 : 0;
+    const double xr = small_ring ? __shfl(xs, ks) : ((judge && lane < L) ? ring[k0] : 0.0);
+    const double x0 = (judge && lane < L) ? xr : 0.0;
     if (cnt == 0) {
       if (lane == 0) gp<uint8_t>(P.pvalid)[idx] = 0;
     } else {
