@@ -19,8 +19,8 @@ the input is integer), favouring obviousness over speed:
                                                  van de Gronde et al. 2016)
 * history flagger ............................. Sec. 4.1 (pseudocode and Fig. "history")
 
-Readings where the paper is silent or garbled are listed in the design doc; each
-function states the reading it implements.  Window sums are brute force
+Where the paper is silent or garbled, each function states the reading it
+implements.  Window sums are brute force
 (a direct sum over each window), the median is a full sort, and integer-input
 comparisons are exact rational comparisons (``fractions.Fraction``).
 """
