@@ -71,6 +71,13 @@ typedef enum {
 #define LOF_OPT_PHASE_TIMING 0x8u        /* record a HIP event after every phase kernel
                                             of each lof_flag_blocks call, for
                                             lof_phase_times (ignored with LOF_OPT_GRAPH) */
+#define LOF_OPT_SIR_PROSE 0x10u          /* the SIR step takes the Sec. 2.2 prose reading:
+                                            every maximal range of L consecutive flagged
+                                            samples gains floor(eta*L) samples before and
+                                            after it (eta = sir_eta_num/sir_eta_den),
+                                            along time, then along frequency on the time
+                                            result; default: the scale-invariant rank
+                                            operator the section cites                 */
 
 /* Phases of the path, in launch order (lof_phase_times) */
 #define LOF_PHASE_STATS 0        /* power, median, stddev, thresholds (Sec. 2.1, 4.2)   */

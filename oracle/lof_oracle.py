@@ -56,6 +56,7 @@ class Params:
     history_len: int = 32
     history_min: int = 4
     literal_history_tie: bool = False  # True: flag when cur >= thr (listing's else-branch)
+    sir_prose: bool = False            # True: the prose reading of Sec. 2.2 (sir_prose_rows)
 
     @property
     def levels_freq(self) -> int:
@@ -226,12 +227,37 @@ def sir_rows(mask: np.ndarray, num: int, den: int) -> np.ndarray:
     return (smax - pmin) >= 0
 
 
+def sir_prose_rows(mask: np.ndarray, num: int, den: int) -> np.ndarray:
+    """The prose reading of Sec. 2.2 along axis 1: every maximal range of consecutive
+    flagged samples in a row, of length L, is extended by floor(eta * L) samples
+    before it and after it (eta = num/den: 20 % -> 1/5), clipped to the row.  The
+    extensions of all ranges of the given mask are combined by OR; they are not
+    applied again to the grown ranges."""
+    R, n = mask.shape
+    out = mask.copy()
+    for r in range(R):
+        y = 0
+        while y < n:
+            if not mask[r, y]:
+                y += 1
+                continue
+            s = y
+            while y < n and mask[r, y]:
+                y += 1
+            ext = (num * (y - s)) // den
+            out[r, max(0, s - ext):min(n, y + ext)] = True
+    return out
+
+
 def sir_block(mask: np.ndarray, params: Params) -> np.ndarray:
-    """SIR in time (rows) then in frequency (columns) on the time result (Sec. 2.2)."""
+    """SIR in time (rows) then in frequency (columns) on the time result (Sec. 2.2);
+    the scale-invariant rank operator, or with ``params.sir_prose`` the range
+    extension the section's prose describes."""
     if params.sir_eta_num == 0:
         return mask.copy()
-    m = sir_rows(mask, params.sir_eta_num, params.sir_eta_den)
-    m = sir_rows(m.T, params.sir_eta_num, params.sir_eta_den).T
+    op = sir_prose_rows if params.sir_prose else sir_rows
+    m = op(mask, params.sir_eta_num, params.sir_eta_den)
+    m = op(m.T, params.sir_eta_num, params.sir_eta_den).T
     return np.ascontiguousarray(m)
 
 

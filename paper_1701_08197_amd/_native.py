@@ -19,6 +19,7 @@ LOF_OPT_AUTOCOMMIT = 0x1
 LOF_OPT_LITERAL_HISTORY_TIE = 0x2
 LOF_OPT_GRAPH = 0x4
 LOF_OPT_PHASE_TIMING = 0x8
+LOF_OPT_SIR_PROSE = 0x10
 # phases of lof_phase_times, in launch order
 PHASES = ("stats", "sumthreshold_time", "sumthreshold_freq", "sir_time", "sir_freq", "history_write")
 LOF_N_PHASES = len(PHASES)

@@ -22,7 +22,51 @@
 #include <vector>
 
 #include "lof.h"
+#include "lof_kernel_table.hpp"
 #include "lof_kernels.hpp"
+
+namespace lofk {
+// zero a few device ints (work counters) without a memset node
+__global__ void lof_zero_kernel(int* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+// Commit staged history values (Sec. 4.1 addToHistory) of a list of streams.
+__global__ void lof_commit_kernel(IdList ids, int all_streams, DevParams P) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nsel = all_streams ? (int64_t)all_streams : (int64_t)ids.n;
+  if (i >= nsel * P.maxC) return;
+  const int si = (int)(i / P.maxC), c = (int)(i - (int64_t)si * P.maxC);
+  const int s = all_streams ? si : ids.ids[si];
+  const int64_t idx = (int64_t)s * P.maxC + c;
+  if (!P.pvalid[idx]) return;
+  const int h = P.rhead[idx];
+  P.ring[idx * P.H + h] = P.pend[idx];
+  P.rhead[idx] = (h + 1 == P.H) ? 0 : h + 1;
+  const int n = P.rcount[idx];
+  P.rcount[idx] = n < P.H ? n + 1 : P.H;
+  P.pvalid[idx] = 0;
+}
+
+// commit for the streams of a descriptor table (automatic commit)
+__global__ void lof_commit_desc_kernel(const DevBlock* __restrict__ blocks, int nb, DevParams P) {
+  const int bi = blockIdx.x;
+  if (bi >= nb) return;
+  const int s = blocks[bi].stream_id;
+  if (s < 0) return;
+  for (int c = threadIdx.x; c < P.maxC; c += blockDim.x) {
+    const int64_t idx = (int64_t)s * P.maxC + c;
+    if (!P.pvalid[idx]) continue;
+    const int h = P.rhead[idx];
+    P.ring[idx * P.H + h] = P.pend[idx];
+    P.rhead[idx] = (h + 1 == P.H) ? 0 : h + 1;
+    const int n = P.rcount[idx];
+    P.rcount[idx] = n < P.H ? n + 1 : P.H;
+    P.pvalid[idx] = 0;
+  }
+}
+
+}  // namespace lofk
 
 using lofk::BlockState;
 using lofk::DevBlock;
@@ -42,6 +86,7 @@ struct Slot {
   DevBlock* d_desc = nullptr;
   DevBlock* h_desc = nullptr;     // pinned
   uint64_t* d_mask = nullptr;
+  uint64_t* d_mask2 = nullptr;    // second mask buffer (LOF_OPT_SIR_PROSE only)
   BlockState* d_state = nullptr;
   uint64_t* d_rowsum = nullptr;   // integer rows' power sums [block][max_channels]
   int* d_counter = nullptr;       // persistent-launch work counters, one per launch
@@ -65,7 +110,7 @@ bool lanes_allowed(int L, int bucket) {
 constexpr int NVAR = 6;   // time layouts: (integer, float) x (32, 48, 64 lanes)
 
 // kernels, for occupancy lookups
-enum KernId { K_STATS = 0, K_TIME = 2, K_FREQ = 8, K_SIRT = 10, K_SIRF = 13, K_FINAL = 14, NKERN = 16 };
+enum KernId { K_STATS = 0, K_TIME = 2, K_FREQ = 8, K_SIRT = 10, K_SIRF = 13, K_FINAL = 14, K_PROSE = 16, NKERN = 18 };
 int variant_lanes(int v) { return v % 3 == 0 ? 32 : (v % 3 == 1 ? 48 : 64); }
 
 size_t elem_size(int dtype) { return dtype == LOF_CI8 ? 2 : (dtype == LOF_F32 ? 4 : 8); }
@@ -116,7 +161,8 @@ struct DevGuard {
   }
 };
 
-DevParams dev_params(const lof_ctx* c, uint64_t* mask, BlockState* state, uint64_t* rowsum, void* stats) {
+DevParams dev_params(const lof_ctx* c, uint64_t* mask, uint64_t* mask2, BlockState* state, uint64_t* rowsum,
+                     void* stats) {
   DevParams P;
   P.start = c->prm.start_threshold;
   P.p = c->prm.p;
@@ -130,12 +176,15 @@ DevParams dev_params(const lof_ctx* c, uint64_t* mask, BlockState* state, uint64
   P.Hmin = c->prm.history_min;
   P.maxC = c->prm.max_channels;
   P.literal = (c->prm.options & LOF_OPT_LITERAL_HISTORY_TIE) ? 1 : 0;
+  P.prose = (c->prm.options & LOF_OPT_SIR_PROSE) ? 1 : 0;
+  P._pad = 0;
   P.ring = c->ring;
   P.rcount = c->rcount;
   P.rhead = c->rhead;
   P.pend = c->pend;
   P.pvalid = c->pvalid;
   P.maskw = mask;
+  P.maskw2 = mask2;
   P.bstate = state;
   P.rowsum = rowsum;
   P.stats = stats;
@@ -171,30 +220,20 @@ lof_status fail(lof_ctx* c, lof_status s, const char* msg) {
 namespace {
 
 const void* kernel_of(int k) {
-  switch (k) {
-    case K_STATS: return (const void*)lofk::lof_stats_kernel<true>;
-    case K_STATS + 1: return (const void*)lofk::lof_stats_kernel<false>;
-    case K_TIME + 0: return (const void*)lofk::lof_time_kernel<true, 32>;
-    case K_TIME + 1: return (const void*)lofk::lof_time_kernel<true, 48>;
-    case K_TIME + 2: return (const void*)lofk::lof_time_kernel<true, 64>;
-    case K_TIME + 3: return (const void*)lofk::lof_time_kernel<false, 32>;
-    case K_TIME + 4: return (const void*)lofk::lof_time_kernel<false, 48>;
-    case K_TIME + 5: return (const void*)lofk::lof_time_kernel<false, 64>;
-    case K_FREQ: return (const void*)lofk::lof_freq_kernel<true>;
-    case K_FREQ + 1: return (const void*)lofk::lof_freq_kernel<false>;
-    case K_SIRT + 0: return (const void*)lofk::lof_sir_time_kernel<32>;
-    case K_SIRT + 1: return (const void*)lofk::lof_sir_time_kernel<48>;
-    case K_SIRT + 2: return (const void*)lofk::lof_sir_time_kernel<64>;
-    case K_SIRF: return (const void*)lofk::lof_sir_freq_kernel;
-    case K_FINAL: return (const void*)lofk::lof_final_kernel<true>;
-    default: return (const void*)lofk::lof_final_kernel<false>;
-  }
+  if (k == K_STATS || k == K_STATS + 1) return lofk::kernel_stats(k == K_STATS);
+  if (k >= K_TIME && k < K_TIME + 6) return lofk::kernel_time(k < K_TIME + 3, variant_lanes(k - K_TIME));
+  if (k == K_FREQ || k == K_FREQ + 1) return lofk::kernel_freq(k == K_FREQ);
+  if (k >= K_SIRT && k < K_SIRT + 3) return lofk::kernel_sir_time(variant_lanes(k - K_SIRT));
+  if (k == K_SIRF) return lofk::kernel_sir_freq();
+  if (k == K_PROSE || k == K_PROSE + 1) return lofk::kernel_prose(k == K_PROSE + 1);
+  return lofk::kernel_final(k == K_FINAL);
 }
 
 void free_slot(Slot& s) {
   if (s.d_desc) (void)hipFree(s.d_desc);
   if (s.h_desc) (void)hipHostFree(s.h_desc);
   if (s.d_mask) (void)hipFree(s.d_mask);
+  if (s.d_mask2) (void)hipFree(s.d_mask2);
   if (s.d_state) (void)hipFree(s.d_state);
   if (s.d_rowsum) (void)hipFree(s.d_rowsum);
   if (s.d_counter) (void)hipFree(s.d_counter);
@@ -204,10 +243,11 @@ void free_slot(Slot& s) {
   s = Slot();
 }
 
-bool alloc_slot(Slot& s, int max_blocks, int max_channels, size_t mask_words, bool timing) {
+bool alloc_slot(Slot& s, int max_blocks, int max_channels, size_t mask_words, bool timing, bool prose) {
   if (timing)
     for (hipEvent_t& e : s.tev)
       if (hipEventCreate(&e) != hipSuccess) return false;
+  if (prose && hipMalloc(&s.d_mask2, sizeof(uint64_t) * mask_words) != hipSuccess) return false;
   return hipMalloc(&s.d_desc, sizeof(DevBlock) * max_blocks) == hipSuccess &&
          hipHostMalloc(&s.h_desc, sizeof(DevBlock) * max_blocks, hipHostMallocDefault) == hipSuccess &&
          hipMalloc(&s.d_mask, sizeof(uint64_t) * mask_words) == hipSuccess &&
@@ -242,7 +282,27 @@ int variant_of(const lof_tuning& t, const lof_block& b) {
   return kind * 3 + lanes_index(t.time_lanes[kind][time_bucket(b.n_times)]);
 }
 
-// validation of one call (all-or-nothing); fills *samples
+// shape, stride, dtype and stream-id range of one block; nullptr when valid
+const char* check_block(const lof_block& b, int max_channels, int max_streams, lof_status* code) {
+  *code = LOF_ERR_INVALID;
+  if (!b.data || !b.flags) return "block data or flags pointer is NULL";
+  if (b.n_channels < 1 || b.n_times < 1) return "block shape must be >= 1 x 1";
+  if (b.n_channels > LOF_MAX_CHANNELS) return "more than 1024 channels";
+  if (b.n_times > MAX_TIMES) return "more than 262144 times";
+  if ((int64_t)b.n_channels * b.n_times > LOF_MAX_BLOCK_SAMPLES) return "block larger than 2^23 samples";
+  if (b.data_row_stride < b.n_times || b.flag_row_stride < b.n_times) return "row stride smaller than n_times";
+  if (b.dtype < LOF_CI8 || b.dtype > LOF_C64_AMP) return "unknown dtype";
+  if (b.stream_id < -1 || b.stream_id >= max_streams) return "stream_id out of range";
+  if (b.n_channels > max_channels) {
+    *code = LOF_ERR_CAPACITY;
+    return "n_channels > max_channels";
+  }
+  return nullptr;
+}
+
+size_t block_mask_words(const lof_block& b) { return (size_t)b.n_channels * (size_t)((b.n_times + 63) / 64); }
+
+// validation of one call (all-or-nothing)
 lof_status validate(lof_ctx* c, const lof_block* blocks, int32_t n, bool check_ids) {
   if (n > c->prm.max_blocks_per_call) return fail(c, LOF_ERR_CAPACITY, "more blocks than max_blocks_per_call");
   c->call_no++;
@@ -254,24 +314,14 @@ lof_status validate(lof_ctx* c, const lof_block* blocks, int32_t n, bool check_i
   size_t words = 0;
   for (int i = 0; i < n; ++i) {
     const lof_block& b = blocks[i];
-    if (!b.data || !b.flags) return fail(c, LOF_ERR_INVALID, "block data or flags pointer is NULL");
-    if (b.n_channels < 1 || b.n_times < 1) return fail(c, LOF_ERR_INVALID, "block shape must be >= 1 x 1");
-    if (b.n_channels > LOF_MAX_CHANNELS) return fail(c, LOF_ERR_INVALID, "more than 1024 channels");
-    if (b.n_channels > c->prm.max_channels) return fail(c, LOF_ERR_CAPACITY, "n_channels > max_channels");
-    if (b.n_times > MAX_TIMES) return fail(c, LOF_ERR_INVALID, "more than 262144 times");
-    if ((int64_t)b.n_channels * b.n_times > LOF_MAX_BLOCK_SAMPLES)
-      return fail(c, LOF_ERR_INVALID, "block larger than 2^23 samples");
-    if (b.data_row_stride < b.n_times || b.flag_row_stride < b.n_times)
-      return fail(c, LOF_ERR_INVALID, "row stride smaller than n_times");
-    if (b.dtype < LOF_CI8 || b.dtype > LOF_C64_AMP) return fail(c, LOF_ERR_INVALID, "unknown dtype");
-    if (b.stream_id < -1 || b.stream_id >= c->prm.max_streams)
-      return fail(c, LOF_ERR_INVALID, "stream_id out of range");
+    lof_status code;
+    if (const char* m = check_block(b, c->prm.max_channels, c->prm.max_streams, &code)) return fail(c, code, m);
     if (check_ids && b.stream_id >= 0) {
       if (c->seen[b.stream_id] == c->call_no) return fail(c, LOF_ERR_INVALID, "stream_id repeated in one call");
       c->seen[b.stream_id] = c->call_no;
     }
     samples += (int64_t)b.n_channels * b.n_times;
-    words += (size_t)b.n_channels * (size_t)((b.n_times + 63) / 64);
+    words += block_mask_words(b);
   }
   if (samples > c->prm.max_samples_per_call)
     return fail(c, LOF_ERR_CAPACITY, "more samples than max_samples_per_call");
@@ -280,9 +330,8 @@ lof_status validate(lof_ctx* c, const lof_block* blocks, int32_t n, bool check_i
 }
 
 // descriptor table in s.h_desc: variant groups, largest block first; counts[v]
-void build_table(lof_ctx* c, const lof_tuning& t, const lof_block* blocks, int32_t n, Slot& s, int* counts,
+void build_table(int* order, const lof_tuning& t, const lof_block* blocks, int32_t n, Slot& s, int* counts,
                  bool history) {
-  int* order = c->order.data();
   for (int i = 0; i < n; ++i) order[i] = i;
   std::sort(order, order + n, [&](int a, int bb) {
     const int va = variant_of(t, blocks[a]), vb = variant_of(t, blocks[bb]);
@@ -356,7 +405,7 @@ int max_chunks(const DevBlock* h, int n, F&& f) {
 // still in s.h_desc, which sizes the chunked launches)
 void enqueue(lof_ctx* c, const lof_tuning& t, Slot& s, const int* counts, int n, void* stats, hipStream_t st,
              bool autocommit, bool timing = false) {
-  const DevParams P = dev_params(c, s.d_mask, s.d_state, s.d_rowsum, stats);
+  const DevParams P = dev_params(c, s.d_mask, s.d_mask2, s.d_state, s.d_rowsum, stats);
   if (t.persistent) hipLaunchKernelGGL(lofk::lof_zero_kernel, dim3(1), dim3(64), 0, st, s.d_counter, NCOUNTER);
   s.ntev = 0;
   if (timing && s.tev[0] && hipEventRecord(s.tev[0], st) == hipSuccess) s.ntev = 1;
@@ -379,7 +428,12 @@ void enqueue(lof_ctx* c, const lof_tuning& t, Slot& s, const int* counts, int n,
     }
     const int mf = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::freq_chunks(integer, b.C, b.T); });
     launch(c, t, K_FREQ + kind, LOF_PHASE_ST_FREQ, dk, kcnt, mf, s, nc, st, P);
-    if (c->prm.sir_eta_num > 0) {
+    if (c->prm.sir_eta_num > 0 && P.prose) {
+      const int mr = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::prose_time_chunks(b.C); });
+      launch(c, t, K_PROSE, LOF_PHASE_SIR_TIME, dk, kcnt, mr, s, nc, st, P);
+      const int mc = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::prose_freq_chunks(b.T); });
+      launch(c, t, K_PROSE + 1, LOF_PHASE_SIR_FREQ, dk, kcnt, mc, s, nc, st, P);
+    } else if (c->prm.sir_eta_num > 0) {
       for (int j = 0, voff = 0; j < 3; voff += counts[3 * kind + j], ++j) {
         const int cnt = counts[3 * kind + j];
         if (cnt) launch(c, t, K_SIRT + j, LOF_PHASE_SIR_TIME, dk + voff, cnt, mt[j], s, nc, st, P);
@@ -494,10 +548,11 @@ lof_status lof_create(const lof_params* params, int hip_device, lof_ctx** out) {
   c->mask_words = (size_t)(params->max_samples_per_call / 64) +
                   (size_t)params->max_blocks_per_call * (size_t)params->max_channels + 64;
   const bool timing = (params->options & LOF_OPT_PHASE_TIMING) && !(params->options & LOF_OPT_GRAPH);
+  const bool prose = (params->options & LOF_OPT_SIR_PROSE) != 0;
   for (int i = 0; ok && i < NSLOT; ++i)
-    ok = alloc_slot(c->slot[i], params->max_blocks_per_call, params->max_channels, c->mask_words, timing);
+    ok = alloc_slot(c->slot[i], params->max_blocks_per_call, params->max_channels, c->mask_words, timing, prose);
   if (ok && (params->options & LOF_OPT_GRAPH)) {
-    ok = alloc_slot(c->gslot, params->max_blocks_per_call, params->max_channels, c->mask_words, false) &&
+    ok = alloc_slot(c->gslot, params->max_blocks_per_call, params->max_channels, c->mask_words, false, prose) &&
          hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
   }
   if (ok) {
@@ -546,7 +601,7 @@ lof_status lof_flag_blocks(lof_ctx* c, const lof_block* blocks, int32_t n, void*
       c->gexec = nullptr;
       c->graph = nullptr;
       c->gvalid = false;
-      build_table(c, c->tune, blocks, n, s, counts, true);
+      build_table(c->order.data(), c->tune, blocks, n, s, counts, true);
       if (hipMemcpy(s.d_desc, s.h_desc, sizeof(DevBlock) * n, hipMemcpyHostToDevice) != hipSuccess)
         return fail(c, LOF_ERR_DEVICE, "descriptor upload failed");
       if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
@@ -577,7 +632,7 @@ lof_status lof_flag_blocks(lof_ctx* c, const lof_block* blocks, int32_t n, void*
     if (hipEventSynchronize(s.ev) != hipSuccess) return fail(c, LOF_ERR_DEVICE, "hipEventSynchronize failed");
     if (!harvest_timing(c, s)) return fail(c, LOF_ERR_DEVICE, "event timing failed");
   }
-  build_table(c, c->tune, blocks, n, s, counts, true);
+  build_table(c->order.data(), c->tune, blocks, n, s, counts, true);
   if (hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(DevBlock) * n, hipMemcpyHostToDevice, st) != hipSuccess)
     return fail(c, LOF_ERR_DEVICE, "descriptor upload failed");
   const bool timing = (c->prm.options & LOF_OPT_PHASE_TIMING) != 0;
@@ -627,7 +682,7 @@ lof_status lof_autotune(lof_ctx* c, const lof_block* blocks, int32_t n, void* hi
   auto time_run = [&](const lof_tuning& t, const std::vector<lof_block>& sub, float* ms) -> bool {
     int counts[NVAR];
     const int m = (int)sub.size();
-    build_table(c, t, sub.data(), m, s, counts, false);
+    build_table(c->order.data(), t, sub.data(), m, s, counts, false);
     if (hipMemcpy(s.d_desc, s.h_desc, sizeof(DevBlock) * m, hipMemcpyHostToDevice) != hipSuccess) return false;
     enqueue(c, t, s, counts, m, nullptr, st, false);   // warm-up
     if (hipEventRecord(e0, st) != hipSuccess) return false;
@@ -696,7 +751,7 @@ lof_status lof_history_update(lof_ctx* c, const int32_t* ids, int32_t n, void* h
   }
   DevGuard g(c->dev);
   hipStream_t st = (hipStream_t)hip_stream;
-  const DevParams P = dev_params(c, nullptr, nullptr, nullptr, nullptr);
+  const DevParams P = dev_params(c, nullptr, nullptr, nullptr, nullptr, nullptr);
   const int TPB = 256;
   if (!ids) {
     lofk::IdList none;

@@ -112,16 +112,21 @@ __host__ __device__ inline int sirf_chunks(int C, int T) {
   return (T + span - 1) / span;
 }
 __host__ __device__ inline int final_chunks(int C) { return (C + NW - 1) / NW; }
+// prose SIR reading: one lane per row (64 rows a wave), one wave per 64-column word
+__host__ __device__ inline int prose_time_chunks(int C) { return (C + NW * 64 - 1) / (NW * 64); }
+__host__ __device__ inline int prose_freq_chunks(int T) { return (((T + 63) >> 6) + NW - 1) / NW; }
 
 struct DevParams {
   double start, p, sens, hs;
   int32_t nl_t, nl_f, eta_num, eta_den, H, Hmin, maxC, literal;
+  int32_t prose, _pad;   // prose: the range-extension reading of the SIR step
   double* ring;          // [streams][maxC][H]
   int32_t* rcount;       // [streams][maxC]
   int32_t* rhead;        // [streams][maxC]
   double* pend;          // [streams][maxC]
   uint8_t* pvalid;       // [streams][maxC]
   uint64_t* maskw;       // mask scratch of this call
+  uint64_t* maskw2;      // second mask buffer (prose SIR reading only)
   BlockState* bstate;    // per-block statistics of this call
   uint64_t* rowsum;      // integer input: [block sidx][maxC] power sum of each row
   void* stats;           // lof_block_stats* or null

@@ -1555,6 +1555,123 @@ __device__ __forceinline__ void phase_sir_freq_l(const DevBlock& b, const DevPar
   }
 }
 
+// ---------------------------------------------------------------- prose reading
+// The range-extension reading of Sec. 2.2: every maximal range of consecutive
+// flagged positions, of length L, gains floor(eta L) positions before and after
+// it; the extensions of all ranges of the input mask are OR-ed.  A forward scan
+// carries `reach`, the end of the furthest right extension of the ranges that
+// have ended, and covers every position below it; a backward scan carries the
+// start of the furthest left extension of the ranges that have begun.  The
+// forward result goes to the second mask buffer, the backward scan reads the
+// input mask and that buffer and writes the result over the input mask.
+struct ProseScan {
+  uint32_t run;   // length of the flagged range the scan is in
+  int reach;
+};
+
+// forward step over one word of positions pos0 .. pos0+nb-1 (bit i <-> pos0+i)
+__device__ __forceinline__ uint64_t prose_fwd_word(uint64_t x, int pos0, int nb, ProseScan& sc, uint32_t num,
+                                                   const FastDiv& fd) {
+  if (x == 0 && sc.run == 0) {
+    const int c = clampi(sc.reach - pos0, 0, nb);
+    return lowmask(c);
+  }
+  if (x == lowmask(nb)) {
+    sc.run += (uint32_t)nb;
+    return x;
+  }
+  uint64_t out = x;
+  for (int i = 0; i < nb; ++i) {
+    if ((x >> i) & 1ull) {
+      ++sc.run;
+    } else {
+      if (sc.run) {
+        sc.reach = max(sc.reach, pos0 + i + (int)fd.div(num * sc.run));
+        sc.run = 0;
+      }
+      if (pos0 + i < sc.reach) out |= 1ull << i;
+    }
+  }
+  return out;
+}
+
+// backward step: positions pos0+nb-1 down to pos0; sc.reach starts at the length
+__device__ __forceinline__ uint64_t prose_bwd_word(uint64_t x, int pos0, int nb, ProseScan& sc, uint32_t num,
+                                                   const FastDiv& fd) {
+  if (x == 0 && sc.run == 0) {
+    const int c = clampi(sc.reach - pos0, 0, nb);   // positions >= reach are covered
+    return lowmask(nb) & ~lowmask(c);
+  }
+  if (x == lowmask(nb)) {
+    sc.run += (uint32_t)nb;
+    return 0;
+  }
+  uint64_t out = 0;
+  for (int i = nb - 1; i >= 0; --i) {
+    if ((x >> i) & 1ull) {
+      ++sc.run;
+    } else {
+      if (sc.run) {
+        sc.reach = min(sc.reach, pos0 + i + 1 - (int)fd.div(num * sc.run));
+        sc.run = 0;
+      }
+      if (pos0 + i >= sc.reach) out |= 1ull << i;
+    }
+  }
+  return out;
+}
+
+// rows: lane = row, 64 rows a wave, words walked in order
+__device__ __forceinline__ void phase_prose_time(const DevBlock& b, const DevParams& P, const int chunk) {
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
+  const int T = b.T, W = (T + 63) >> 6;
+  const int row = (chunk * NW + wv) * 64 + lane;
+  if (row >= b.C || P.eta_num == 0) return;
+  GLB uint64_t* mrow = gp<uint64_t>(P.maskw) + b.mask_off + (int64_t)row * W;
+  GLB uint64_t* brow = gp<uint64_t>(P.maskw2) + b.mask_off + (int64_t)row * W;
+  const FastDiv fd((uint32_t)P.eta_den);
+  const uint32_t num = (uint32_t)P.eta_num;
+  ProseScan f{0u, 0};
+  for (int w = 0; w < W; ++w) {
+    const int nb = min(64, T - 64 * w);
+    brow[w] = prose_fwd_word(mrow[w] & lowmask(nb), 64 * w, nb, f, num, fd);
+  }
+  ProseScan r{0u, T};
+  for (int w = W - 1; w >= 0; --w) {
+    const int nb = min(64, T - 64 * w);
+    const uint64_t x = mrow[w] & lowmask(nb);
+    mrow[w] = brow[w] | prose_bwd_word(x, 64 * w, nb, r, num, fd);
+  }
+}
+
+// columns: lane = column of one 64-column word (wave-uniform), channels walked
+// in order, each channel's word of the result assembled by a ballot
+__device__ __forceinline__ void phase_prose_freq(const DevBlock& b, const DevParams& P, const int chunk) {
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
+  const int T = b.T, C = b.C, W = (T + 63) >> 6;
+  const int wi = chunk * NW + wv;
+  if (wi >= W || C <= 1 || P.eta_num == 0) return;
+  GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off + wi;
+  GLB uint64_t* b0 = gp<uint64_t>(P.maskw2) + b.mask_off + wi;
+  const bool ok = wi * 64 + lane < T;
+  const FastDiv fd((uint32_t)P.eta_den);
+  const uint32_t num = (uint32_t)P.eta_num;
+  ProseScan f{0u, 0};
+  for (int c = 0; c < C; ++c) {
+    const uint64_t x = m0[(int64_t)c * W];
+    const uint64_t o = prose_fwd_word(ok ? ((x >> lane) & 1ull) : 0ull, c, 1, f, num, fd);
+    const uint64_t word = __ballot(o != 0);
+    if (lane == 0) b0[(int64_t)c * W] = word;
+  }
+  ProseScan r{0u, C};
+  for (int c = C - 1; c >= 0; --c) {
+    const uint64_t x = m0[(int64_t)c * W];
+    const uint64_t o = prose_bwd_word(ok ? ((x >> lane) & 1ull) : 0ull, c, 1, r, num, fd);
+    const uint64_t word = __ballot(o != 0);
+    if (lane == 0) m0[(int64_t)c * W] = b0[(int64_t)c * W] | word;
+  }
+}
+
 // flag bytes of one row word: nv (<= 64) samples from t0, bit j -> byte j
 __device__ __forceinline__ void write_word_bytes(const DevBlock& b, int row, int t0, int nv, uint64_t w) {
   GLB uint8_t* fp = gp<uint8_t>(b.flags) + (int64_t)row * b.fstride + t0;
@@ -1580,7 +1697,9 @@ __device__ __forceinline__ void write_word_bytes(const DevBlock& b, int row, int
 // flags go back through the transpose.  This is the last pass over the mask, so
 // it also writes the flag bytes of its 64 columns (the history pass rewrites
 // only rows it flags) and counts the flagged samples.
-__host__ __device__ inline bool sirf_writes_bytes(int eta_num, int C) { return eta_num > 0 && C > 1 && C <= 64; }
+__host__ __device__ inline bool sirf_writes_bytes(int eta_num, int prose, int C) {
+  return eta_num > 0 && !prose && C > 1 && C <= 64;
+}
 
 __device__ __forceinline__ void phase_sir_freq_col(const DevBlock& b, const DevParams& P, const int chunk) {
   const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
@@ -1958,17 +2077,6 @@ __global__ __launch_bounds__(WG, LOF_SIRT_WAVES_PER_EU) void lof_sir_time_kernel
   });
 }
 
-__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_sir_freq_kernel(const DevBlock* __restrict__ blocks, int nb,
-                                                                            int maxch, int* counter, DevParams P) {
-  __shared__ SmSirF sm;
-  run_items(nb * maxch, counter, [&](int it) __attribute__((always_inline)) {
-    const int bi = it / maxch, ch = it - bi * maxch;
-    const DevBlock b = blocks[bi];
-    if (ch >= sirf_chunks(b.C, b.T)) return;
-    phase_sir_freq(b, P, sm, ch);
-  });
-}
-
 // Phase D: history flagger and flag bytes, rows in chunks of NW
 template <bool INT>
 __global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_final_kernel(const DevBlock* __restrict__ blocks, int nb,
@@ -1980,13 +2088,8 @@ __global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_final_kernel(const D
     if (ch >= final_chunks(b.C)) return;
     const int r0 = ch * NW, r1 = min(b.C, r0 + NW);
     phase_history<INT>(b, P, sm, r0, r1);
-    phase_write(b, P, sm, r0, r1, sirf_writes_bytes(P.eta_num, b.C));
+    phase_write(b, P, sm, r0, r1, sirf_writes_bytes(P.eta_num, P.prose, b.C));
   });
-}
-
-// zero a few device ints (work counters) without a memset node
-__global__ void lof_zero_kernel(int* p, int n) {
-  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
 // Commit staged history values (Sec. 4.1 addToHistory) of a list of streams.
@@ -1994,39 +2097,5 @@ struct IdList {
   int32_t n;
   int32_t ids[255];
 };
-
-__global__ void lof_commit_kernel(IdList ids, int all_streams, DevParams P) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nsel = all_streams ? (int64_t)all_streams : (int64_t)ids.n;
-  if (i >= nsel * P.maxC) return;
-  const int si = (int)(i / P.maxC), c = (int)(i - (int64_t)si * P.maxC);
-  const int s = all_streams ? si : ids.ids[si];
-  const int64_t idx = (int64_t)s * P.maxC + c;
-  if (!P.pvalid[idx]) return;
-  const int h = P.rhead[idx];
-  P.ring[idx * P.H + h] = P.pend[idx];
-  P.rhead[idx] = (h + 1 == P.H) ? 0 : h + 1;
-  const int n = P.rcount[idx];
-  P.rcount[idx] = n < P.H ? n + 1 : P.H;
-  P.pvalid[idx] = 0;
-}
-
-// commit for the streams of a descriptor table (automatic commit)
-__global__ void lof_commit_desc_kernel(const DevBlock* __restrict__ blocks, int nb, DevParams P) {
-  const int bi = blockIdx.x;
-  if (bi >= nb) return;
-  const int s = blocks[bi].stream_id;
-  if (s < 0) return;
-  for (int c = threadIdx.x; c < P.maxC; c += blockDim.x) {
-    const int64_t idx = (int64_t)s * P.maxC + c;
-    if (!P.pvalid[idx]) continue;
-    const int h = P.rhead[idx];
-    P.ring[idx * P.H + h] = P.pend[idx];
-    P.rhead[idx] = (h + 1 == P.H) ? 0 : h + 1;
-    const int n = P.rcount[idx];
-    P.rcount[idx] = n < P.H ? n + 1 : P.H;
-    P.pvalid[idx] = 0;
-  }
-}
 
 }  // namespace lofk

@@ -107,10 +107,11 @@ def config0():
 
 
 # ------------------------------------------------------------------------ cfg 1
-def _pulse_profile(subband: int, C: int, T: int, n_subbands: int = 64):
+def _pulse_profile(subband: int, C: int, T: int, n_subbands: int = 64, t_start: float = 0.0):
     """Weak dispersed periodic pulse (DM 30, period 0.714 s, 10 ms wide) over 64
     contiguous 195.3125 kHz subbands centred at 150 MHz, 64 channels each,
-    327.68 us samples.  Returns a bool [C, T] on-pulse mask."""
+    327.68 us samples, for the block starting t_start seconds into the
+    observation.  Returns a bool [C, T] on-pulse mask."""
     df_sb = 195.3125e3
     df_ch = df_sb / C
     tsamp = 1.0 / df_ch
@@ -119,7 +120,7 @@ def _pulse_profile(subband: int, C: int, T: int, n_subbands: int = 64):
     f = f_lo + subband * df_sb + (np.arange(C) + 0.5) * df_ch
     dm, period, width, t_first = 30.0, 0.714, 10e-3, 0.05
     delay = 4.1488e-3 * dm * ((f / 1e9) ** -2 - (f_top / 1e9) ** -2)
-    t = np.arange(T) * tsamp
+    t = t_start + np.arange(T) * tsamp
     on = np.zeros((C, T), dtype=bool)
     for c in range(C):
         ph = np.mod(t - t_first - delay[c], period)
@@ -129,7 +130,7 @@ def _pulse_profile(subband: int, C: int, T: int, n_subbands: int = 64):
 
 def ci8_block(rng: np.random.Generator, C: int, T: int, sigma: float = CFG1_SIGMA,
               rfi: bool = True, pulse_subband: int | None = None,
-              pulse_k: float = 0.2) -> np.ndarray:
+              pulse_k: float = 0.2, pulse_t0: float = 0.0) -> np.ndarray:
     """Complex int8 voltages [C, T, 2] (re, im): Gaussian with per-component sigma,
     the RFI mix and an optional weak pulse added before rounding half-to-even and
     clipping to +-127."""
@@ -139,7 +140,7 @@ def ci8_block(rng: np.random.Generator, C: int, T: int, sigma: float = CFG1_SIGM
     if rfi:
         _add_rfi_voltage(rng, re, im, rfi_plan(rng, C, T), noise_power)
     if pulse_subband is not None:
-        on = _pulse_profile(pulse_subband, C, T)
+        on = _pulse_profile(pulse_subband, C, T, t_start=pulse_t0)
         amp = np.float32(np.sqrt(pulse_k * noise_power))
         ph = rng.uniform(0, 2 * np.pi, size=int(on.sum())).astype(np.float32)
         re[on] += amp * np.cos(ph)
@@ -154,10 +155,16 @@ def config1_index(station: int, pol: int, subband: int) -> int:
     return (station * CFG1_POLS + pol) * CFG1_SUBBANDS + subband
 
 
-def config1_block(b: int) -> np.ndarray:
-    """Block b = (station * 2 + pol) * 64 + subband of the 48-station second."""
+CFG1_SECOND_S = CFG1_T * CFG1_C / 195.3125e3   # 3072 samples of 327.68 us
+
+
+def config1_block(b: int, second: int = 0) -> np.ndarray:
+    """Block b = (station * 2 + pol) * 64 + subband of second `second` of the
+    48-station observation (each second has its own noise, RFI and pulse phase)."""
     subband = b % CFG1_SUBBANDS
-    return ci8_block(rng_for(1, b), CFG1_C, CFG1_T, pulse_subband=subband)
+    idx = b if second == 0 else second * CFG1_STATIONS * CFG1_POLS * CFG1_SUBBANDS + b
+    return ci8_block(rng_for(1, idx), CFG1_C, CFG1_T, pulse_subband=subband,
+                     pulse_t0=second * CFG1_SECOND_S)
 
 
 CONFIG1_BLOCKS = CFG1_STATIONS * CFG1_POLS * CFG1_SUBBANDS   # 6144

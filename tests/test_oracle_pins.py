@@ -368,6 +368,79 @@ def test_sir_block_is_time_then_frequency():
     assert (got == expect).all()
 
 
+# The prose reading of Sec. 2.2 (LOF_OPT_SIR_PROSE): every maximal range of
+# consecutive flagged samples, of length L, gains floor(eta L) samples before and
+# after it.  Pinned by hand-worked rows and by an independent per-position check
+# of that sentence.
+@pytest.mark.parametrize("L,ext", [(1, 0), (4, 0), (5, 1), (9, 1), (10, 2), (14, 2), (15, 3), (40, 8)])
+def test_sir_prose_isolated_run(L, ext):
+    n = 120
+    m = np.zeros(n, dtype=bool)
+    m[50:50 + L] = True
+    out = O.sir_prose_rows(m[None, :], 1, 5)[0]
+    expect = np.zeros(n, dtype=bool)
+    expect[50 - ext:50 + L + ext] = True
+    assert (out == expect).all()
+
+
+def test_sir_prose_hand_worked_rows():
+    def row(txt):
+        return np.array([c == "1" for c in txt])
+    cases = [
+        # a run of 10 at the start is clipped on the left, grows 2 on the right
+        ("111111111100000000", "111111111111000000"),
+        # runs of 10 and 5 three apart: [0, 12) and [12, 19) join
+        ("11111111110001111100000", "11111111111111111110000"),
+        # short runs (L < 5) do not grow, whatever their neighbours
+        ("0011101101110000", "0011101101110000"),
+        # a run of 5 at the end grows by 1 on the left only
+        ("0000000011111", "0000000111111"),
+    ]
+    for src, want in cases:
+        got = O.sir_prose_rows(row(src)[None, :], 1, 5)[0]
+        assert "".join("1" if v else "0" for v in got) == want, src
+
+
+def _prose_by_definition(m, num, den):
+    # y is flagged iff it lies in [s - floor(eta L), e + floor(eta L)) of some
+    # maximal flagged range [s, e) of length L = e - s
+    n = len(m)
+    edges = np.diff(np.concatenate([[0], m.astype(np.int8), [0]]))
+    starts = np.flatnonzero(edges == 1)
+    ends = np.flatnonzero(edges == -1)
+    y = np.arange(n)
+    out = np.zeros(n, dtype=bool)
+    for s_, e_ in zip(starts, ends):
+        ext = (num * (e_ - s_)) // den
+        out |= (y >= s_ - ext) & (y < e_ + ext)
+    return out
+
+
+@pytest.mark.parametrize("num,den", [(1, 5), (1, 2), (3, 7), (0, 1), (1, 1)])
+def test_sir_prose_equals_definition(num, den):
+    rng = np.random.default_rng(100 + num * 10 + den)
+    for _ in range(200):
+        n = int(rng.integers(1, 90))
+        m = rng.random(n) < rng.uniform(0.05, 0.9)
+        got = O.sir_prose_rows(m[None, :], num, den)[0]
+        assert (got == _prose_by_definition(m, num, den)).all(), (m.astype(int), num, den)
+
+
+def test_sir_prose_differs_from_operator_and_orders_directions():
+    # L = 20: the operator grows floor(L/4) = 5 per side, the prose reading floor(L/5) = 4
+    m = np.zeros(60, dtype=bool)
+    m[20:40] = True
+    assert O.sir_rows(m[None], 1, 5)[0].sum() == 30
+    assert O.sir_prose_rows(m[None], 1, 5)[0].sum() == 28
+    rng = np.random.default_rng(8)
+    blk = rng.random((11, 37)) < 0.3
+    got = O.sir_block(blk, O.Params(sir_prose=True))
+    rows = np.array([_prose_by_definition(r, 1, 5) for r in blk])
+    expect = np.array([_prose_by_definition(c, 1, 5) for c in rows.T]).T
+    assert (got == expect).all()
+    assert (O.sir_block(blk, O.Params(sir_prose=True, sir_eta_num=0)) == blk).all()
+
+
 def test_sir_percentage_from_paper():
     g = golden()
     prm = O.Params()
