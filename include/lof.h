@@ -225,8 +225,33 @@ lof_status lof_phase_times(lof_ctx* ctx, double* ms, int32_t* n_calls);
  * it.  NULL is a no-op. */
 lof_status lof_destroy(lof_ctx* ctx);
 
-/* Static, NUL-terminated description of the last error on ctx (or of the last
- * failed lof_create when ctx is NULL). */
+/* Allocation-free variant of lof_flag_blocks, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): it needs no lof_ctx, and it neither allocates nor
+ * frees anything.  Its scratch (descriptor table, per-block statistics, row
+ * sums and mask words) is one file-scope device array of 32 MiB per GPU, which
+ * stays allocated until the process ends.  The blocks are flagged exactly as
+ * lof_flag_blocks flags them with the same `params`, except that there is no
+ * history flagger: every stream_id must be -1.  Capacity: at most 4096 blocks
+ * and at most what fits the 32 MiB: 256-byte-aligned areas of 72 B per block
+ * (descriptors), 144 B per block (statistics), 8 B x n_blocks x (largest C) (row
+ * sums), 128 B (counters), and 8 B per 64 samples of every row (mask words), e.g.
+ * 160 blocks of 64 x 3072 or 3.9e6 words of rows whose length is a multiple of 64.
+ * `params` is read during the call (its capacity and option fields are not used);
+ * `blocks`, `stats`, `hip_stream` are as in lof_flag_blocks, on device
+ * `hip_device`.  Every call on one GPU shares that GPU's scratch array: calls
+ * whose work overlaps on one GPU (different host threads, or different HIP
+ * streams) race and give wrong flags; the caller serialises them (the host side
+ * also serialises concurrent calls).  Errors (nothing enqueued):
+ * LOF_ERR_INVALID (bad params, blocks, device, or a stream_id other than -1),
+ * LOF_ERR_CAPACITY (over the limits above), LOF_ERR_DEVICE (HIP failure);
+ * lof_last_error(NULL) describes the failure. */
+lof_status lof_flag_blocks_static(const lof_params* params, int hip_device, const lof_block* blocks,
+                                  int32_t n_blocks, void* hip_stream, lof_block_stats* stats);
+
+/* Static, NUL-terminated description of the last error on ctx (or, when ctx is
+ * NULL, of the last failed lof_create or lof_flag_blocks_static on this host
+ * thread). */
 const char* lof_last_error(const lof_ctx* ctx);
 
 #ifdef __cplusplus

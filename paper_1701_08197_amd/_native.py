@@ -28,7 +28,7 @@ LOF_TUNE_BUCKETS = 5
 
 EXPORTED = ("lof_default_params", "lof_create", "lof_flag_blocks", "lof_history_update",
             "lof_history_export", "lof_get_tuning", "lof_set_tuning", "lof_autotune", "lof_phase_times",
-            "lof_destroy", "lof_last_error")
+            "lof_destroy", "lof_last_error", "lof_flag_blocks_static")
 
 
 class LofParams(ctypes.Structure):
@@ -132,6 +132,9 @@ def load() -> ctypes.CDLL:
     L.lof_destroy.restype = ctypes.c_int
     L.lof_phase_times.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
     L.lof_phase_times.restype = ctypes.c_int
+    L.lof_flag_blocks_static.argtypes = [ctypes.POINTER(LofParams), ctypes.c_int, ctypes.POINTER(LofBlock),
+                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    L.lof_flag_blocks_static.restype = ctypes.c_int
     L.lof_last_error.argtypes = [ctypes.c_void_p]
     L.lof_last_error.restype = ctypes.c_char_p
     _lib = L

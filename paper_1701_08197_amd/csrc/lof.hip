@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -66,6 +68,23 @@ __global__ void lof_commit_desc_kernel(const DevBlock* __restrict__ blocks, int 
   }
 }
 
+// Allocation-free entry point (lof_flag_blocks_static): the per-call scratch of
+// the phase kernels (descriptor table, per-block statistics, integer row sums,
+// mask words) lives in this one file-scope array, one copy per GPU, held until
+// the process ends.  Host code uses its device address from hipGetSymbolAddress.
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+// descriptors travel as kernel arguments (no host staging buffer, no copy)
+constexpr int DESC_CHUNK = 32;
+struct DescChunk {
+  int32_t n, first;
+  DevBlock d[DESC_CHUNK];
+};
+__global__ void lof_put_desc_kernel(DevBlock* dst, DescChunk ch) {
+  const int i = (int)threadIdx.x;
+  if (i < ch.n) dst[ch.first + i] = ch.d[i];
+}
 }  // namespace lofk
 
 using lofk::BlockState;
@@ -825,5 +844,95 @@ lof_status lof_phase_times(lof_ctx* c, double* ms, int32_t* n_calls) {
 }
 
 const char* lof_last_error(const lof_ctx* c) { return c ? c->err : g_create_err; }
+
+// ---------------------------------------------------------------- allocation-free entry point
+namespace {
+constexpr int STATIC_MAX_DEVICES = 64;
+constexpr int STATIC_MAX_BLOCKS = 4096;
+std::atomic<void*> g_static_scratch[STATIC_MAX_DEVICES];
+// host-side descriptor staging, in static storage; one call at a time builds it
+std::mutex g_static_mu;
+int g_static_order[STATIC_MAX_BLOCKS];
+DevBlock g_static_desc[STATIC_MAX_BLOCKS];
+
+lof_status static_fail(lof_status s, const char* m) {
+  g_create_err = m;
+  return s;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // namespace
+
+lof_status lof_flag_blocks_static(const lof_params* params, int hip_device, const lof_block* blocks,
+                                  int32_t n_blocks, void* hip_stream, lof_block_stats* stats) {
+  if (const char* m = check_params(params)) return static_fail(LOF_ERR_INVALID, m);
+  if (n_blocks < 0) return static_fail(LOF_ERR_INVALID, "n_blocks < 0");
+  if (n_blocks == 0) return LOF_OK;
+  if (!blocks) return static_fail(LOF_ERR_INVALID, "blocks is NULL");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev ||
+      hip_device >= STATIC_MAX_DEVICES)
+    return static_fail(LOF_ERR_INVALID, "no such HIP device");
+  if (n_blocks > STATIC_MAX_BLOCKS) return static_fail(LOF_ERR_CAPACITY, "more than 4096 blocks");
+  int maxC = 1;
+  size_t words = 0;
+  for (int i = 0; i < n_blocks; ++i) {
+    lof_status code;
+    if (const char* m = check_block(blocks[i], LOF_MAX_CHANNELS, 1, &code)) return static_fail(code, m);
+    if (blocks[i].stream_id != -1) return static_fail(LOF_ERR_INVALID, "no history here: stream_id must be -1");
+    maxC = std::max(maxC, blocks[i].n_channels);
+    words += block_mask_words(blocks[i]);
+  }
+  // carve the scratch array: descriptors, block statistics, row sums, work counters, mask words
+  const size_t o_desc = 0;
+  const size_t o_state = align256(o_desc + sizeof(DevBlock) * n_blocks);
+  const size_t o_rowsum = align256(o_state + sizeof(BlockState) * n_blocks);
+  const size_t o_counter = align256(o_rowsum + sizeof(uint64_t) * (size_t)n_blocks * maxC);
+  const size_t o_mask = align256(o_counter + sizeof(int) * NCOUNTER);
+  const bool prose = (params->options & LOF_OPT_SIR_PROSE) != 0 && params->sir_eta_num > 0;
+  const size_t o_mask2 = align256(o_mask + sizeof(uint64_t) * words);
+  const size_t need = prose ? o_mask2 + sizeof(uint64_t) * words : o_mask + sizeof(uint64_t) * words;
+  if (need > lofk::STATIC_SCRATCH_BYTES) return static_fail(LOF_ERR_CAPACITY, "call needs more than the 32 MiB static scratch");
+
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  DevGuard g(hip_device);
+  void* base = g_static_scratch[hip_device].load();
+  if (!base) {
+    if (hipGetSymbolAddress(&base, HIP_SYMBOL(lofk::scratch)) != hipSuccess || !base) {
+      (void)hipGetLastError();
+      return static_fail(LOF_ERR_DEVICE, "hipGetSymbolAddress of the static scratch failed");
+    }
+    g_static_scratch[hip_device].store(base);
+  }
+  unsigned char* sp = (unsigned char*)base;
+  hipStream_t st = (hipStream_t)hip_stream;
+
+  lof_ctx c;                     // launch configuration only: owns no memory
+  c.prm = *params;
+  c.prm.max_channels = maxC;     // row sums are indexed [block][maxC]
+  c.prm.options &= ~(uint32_t)(LOF_OPT_AUTOCOMMIT | LOF_OPT_GRAPH | LOF_OPT_PHASE_TIMING);
+  default_tuning(&c.tune);
+  Slot s;
+  s.d_desc = (DevBlock*)(sp + o_desc);
+  s.h_desc = g_static_desc;
+  s.d_state = (BlockState*)(sp + o_state);
+  s.d_rowsum = (uint64_t*)(sp + o_rowsum);
+  s.d_counter = (int*)(sp + o_counter);
+  s.d_mask = (uint64_t*)(sp + o_mask);
+  s.d_mask2 = prose ? (uint64_t*)(sp + o_mask2) : nullptr;
+  int counts[NVAR];
+  build_table(g_static_order, c.tune, blocks, n_blocks, s, counts, false);
+  for (int i = 0; i < n_blocks; i += lofk::DESC_CHUNK) {
+    lofk::DescChunk ch;
+    ch.n = std::min(lofk::DESC_CHUNK, n_blocks - i);
+    ch.first = i;
+    std::memcpy(ch.d, s.h_desc + i, sizeof(DevBlock) * ch.n);
+    hipLaunchKernelGGL(lofk::lof_put_desc_kernel, dim3(1), dim3(lofk::DESC_CHUNK), 0, st, s.d_desc, ch);
+  }
+  enqueue(&c, c.tune, s, counts, n_blocks, stats, st, false);
+  if (hipGetLastError() != hipSuccess) return static_fail(LOF_ERR_DEVICE, "kernel launch failed");
+  return LOF_OK;
+}
+
 
 }  // extern "C"

@@ -165,6 +165,20 @@ class Flagger:
             pass
 
 
+def flag_blocks_static(params: N.LofParams, blocks, device: int = 0, stream=None, stats=None) -> None:
+    """lof_flag_blocks_static: flags ``blocks`` (Block or LofBlock, stream ids -1)
+    with the library's own static scratch; nothing is allocated."""
+    L = N.load()
+    n = len(blocks)
+    arr = (N.LofBlock * max(1, n))()
+    for i, b in enumerate(blocks):
+        arr[i] = b if isinstance(b, N.LofBlock) else b.to_c()
+    sp = None if stats is None else stats.data_ptr()
+    st = L.lof_flag_blocks_static(ctypes.byref(params), device, arr, n, _stream_handle(stream), sp)
+    if st != N.LOF_OK:
+        raise LofError(st, L.lof_last_error(None).decode())
+
+
 def decode_stats(raw_bytes) -> list:
     """Decode a host copy of the stats buffer into dicts."""
     n = len(raw_bytes) // N.STATS_BYTES
