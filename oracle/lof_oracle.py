@@ -18,6 +18,7 @@ the input is integer), favouring obviousness over speed:
 * scale-invariant rank (SIR) operator ......... Sec. 2.2 (and its cited linear algorithm,
                                                  van de Gronde et al. 2016)
 * history flagger ............................. Sec. 4.1 (pseudocode and Fig. "history")
+* integrated pre-correlation mode ............. Sec. 4 (integration paragraph, Fig. "integrate")
 
 Where the paper is silent or garbled, each function states the reading it
 implements.  Window sums are brute force
@@ -357,6 +358,95 @@ def flag_block(x: np.ndarray, dtype: int, params: Params = Params(),
                 history.pending[(stream_id, c)] = pv
     flags = sm | hrows[:, None]
     return BlockResult(flags, med, sd, th, st, sm, hrows, pend)
+
+
+# ------------------------------------------------------------- integrated mode
+def series_stddev(v: np.ndarray, exact: bool) -> float:
+    """Population standard deviation of a 1-D series with the formula of
+    block_stddev; integer series use Python integers throughout (their squares
+    can exceed 64 bits), and mu = S1/N, E[x^2] = S2/N are the correctly rounded
+    quotients."""
+    n = v.size
+    if exact:
+        s1 = sum(int(a) for a in v.tolist())
+        s2 = sum(int(a) * int(a) for a in v.tolist())
+        mu = s1 / n
+        ex2 = s2 / n
+    else:
+        mu = math.fsum(v.tolist()) / n
+        ex2 = math.fsum((v * v).tolist()) / n
+    var = ex2 - mu * mu
+    if var < 0.0:
+        var = 0.0
+    return math.sqrt(var)
+
+
+def flag_series(v: np.ndarray, params: Params, exact: bool, n_levels: int) -> np.ndarray:
+    """Flags of one integrated 1-D series: its own median and stddev, the
+    thresholds of Sec. 2.1, one-dimensional SumThreshold, then the SIR step
+    (Sec. 2.2) on the series' mask."""
+    med = block_median(v)
+    sd = series_stddev(v, exact)
+    th = thresholds(med, sd, params, max(1, n_levels))
+    m = sumthreshold_rows(v[None, :], np.zeros((1, v.size), dtype=bool), th, n_levels, exact)
+    if params.sir_eta_num > 0:
+        op = sir_prose_rows if params.sir_prose else sir_rows
+        m = op(m, params.sir_eta_num, params.sir_eta_den)
+    return m[0]
+
+
+@dataclass
+class IntegratedResult:
+    flags: np.ndarray          # bool [C, T]: channel flags OR time flags (then history rows)
+    channel_flags: np.ndarray  # bool [C]
+    time_flags: np.ndarray     # bool [T]
+    spectrum: np.ndarray       # [C] time-integrated power
+    series: np.ndarray         # [T] frequency-integrated power of the unflagged channels
+    history_rows: np.ndarray
+    pending: list
+
+
+def integrated_block(x: np.ndarray, dtype: int, params: Params = Params(),
+                     history: History | None = None, stream_id: int = -1) -> IntegratedResult:
+    """Integrated pre-correlation mode (Sec. 4, integration paragraph): integrate
+    time fully and flag the spectrum along frequency first (this removes strong
+    narrow-band RFI before the time statistics are formed), then integrate the
+    unflagged channels fully and flag the time series along time; a flagged
+    channel flags its whole row, a flagged time flags its whole column.  Sums are
+    exact integers for complex int8 input, float64 otherwise.  The history
+    flagger (Sec. 4.1) then runs on the result as in flag_block."""
+    exact = is_exact(dtype)
+    p = power(x, dtype)
+    C, T = p.shape
+    if exact:
+        spec = p.sum(axis=1, dtype=np.int64)
+    else:
+        spec = np.array([math.fsum(r.tolist()) for r in p])
+    chan = flag_series(spec, params, exact, min(params.levels_freq, ST_LEVELS_MAX))
+    keep = ~chan
+    if exact:
+        series = p[keep].sum(axis=0, dtype=np.int64) if keep.any() else np.zeros(T, dtype=np.int64)
+    else:
+        series = (np.array([math.fsum(col.tolist()) for col in p[keep].T]) if keep.any()
+                  else np.zeros(T))
+    tim = flag_series(series, params, exact, min(params.n_levels, ST_LEVELS_MAX))
+    m = chan[:, None] | tim[None, :]
+    hrows = np.zeros(C, dtype=bool)
+    pend = [None] * C
+    if history is not None and stream_id >= 0:
+        for c in range(C):
+            unfl = ~m[c]
+            n_u = int(unfl.sum())
+            s = int(np.sum(p[c][unfl], dtype=np.int64)) if exact else math.fsum(p[c][unfl].tolist())
+            f, pv = history_row(s, n_u, history.ring(stream_id, c), params)
+            hrows[c] = f
+            pend[c] = pv
+            if pv is not None:
+                history.pending[(stream_id, c)] = pv
+    return IntegratedResult(m | hrows[:, None], chan, tim, spec, series, hrows, pend)
+
+
+ST_LEVELS_MAX = 7   # windows up to 64 samples
 
 
 # ----------------------------------------------------------------------- sizing aid

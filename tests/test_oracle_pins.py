@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import oracle.lof_oracle as O
+import synth
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
 
@@ -528,3 +529,91 @@ def test_injected_rfi_is_found_config0_shape():
         if kind in ("tone", "impulse"):
             assert frac > 0.9, (kind, frac)
     assert r.flags.mean() < 0.2
+
+
+# ------------------------------------------------------------ integrated mode
+# Sec. 4 (integration paragraph): the spectrum (time fully integrated) is
+# flagged along frequency first, then the time series of the unflagged channels
+# (frequency fully integrated) along time; flags are broadcast back.
+def _ci8_from_power(pw):
+    """complex int8 block whose power re^2 + im^2 is exactly `pw` (pw = re^2,
+    values that are squares of 0..127)."""
+    re = np.sqrt(pw).astype(np.int64)
+    assert (re * re == pw).all()
+    x = np.zeros(pw.shape + (2,), dtype=np.int8)
+    x[..., 0] = re
+    return x
+
+
+def test_integrated_constant_block_flags_nothing():
+    x = _ci8_from_power(np.full((16, 200), 49, dtype=np.int64))
+    r = O.integrated_block(x, O.CI8)
+    assert not r.flags.any()
+    assert (r.spectrum == 49 * 200).all() and (r.series == 49 * 16).all()
+
+
+@pytest.mark.parametrize("T,flagged", [(34, False), (35, True), (64, True)])
+def test_integrated_broadband_impulse_closed_form(T, flagged):
+    # zero background, one time column of power 25 in every channel: the spectrum
+    # is constant (no channel flags) and the time series is a single impulse on a
+    # zero background, flagged iff its length is at least 35 (N/sqrt(N-1) > 6)
+    pw = np.zeros((8, T), dtype=np.int64)
+    pw[:, T // 2] = 25
+    r = O.integrated_block(_ci8_from_power(pw), O.CI8, O.Params(sir_eta_num=0))
+    assert not r.channel_flags.any()
+    expect = np.zeros(T, dtype=bool)
+    expect[T // 2] = flagged
+    assert (r.time_flags == expect).all()
+    assert (r.flags == expect[None, :]).all()
+
+
+def test_integrated_removes_narrowband_rfi_before_the_time_series():
+    # background power 1; channel 3 carries a tone of power 100 with two bursts of
+    # 10000.  The spectrum flags channel 3; the time series of the other channels
+    # is then constant and nothing else is flagged.  Left in, the tone's bursts
+    # would flag their two times in every channel.
+    C, T = 40, 128
+    pw = np.ones((C, T), dtype=np.int64)
+    pw[3] = 100
+    pw[3, [20, 90]] = 10000
+    x = _ci8_from_power(pw)
+    prm = O.Params(sir_eta_num=0)
+    r = O.integrated_block(x, O.CI8, prm)
+    assert r.channel_flags.nonzero()[0].tolist() == [3]
+    assert not r.time_flags.any()
+    assert (r.flags == (np.arange(C) == 3)[:, None]).all()
+    assert O.flag_series(pw.sum(axis=0), prm, True, 7).nonzero()[0].tolist() == [20, 90]
+
+
+def test_integrated_finds_a_weak_tone_full_rate_misses():
+    # a +0.25 sigma narrowband tone in unit complex noise: below the full-rate
+    # thresholds at every window size, but 2048 integrated samples lift it clear
+    # of the spectrum's noise
+    rng = np.random.default_rng(17)
+    C, T = 128, 2048
+    s = np.float32(np.sqrt(0.5))
+    z = (rng.standard_normal((C, T), dtype=np.float32) * s
+         + 1j * rng.standard_normal((C, T), dtype=np.float32) * s).astype(np.complex64)
+    z[11] += np.complex64(0.5) * np.exp(1j * rng.uniform(0, 2 * np.pi, T)).astype(np.complex64)
+    prm = O.Params(sir_eta_num=0)
+    full = O.flag_block(z, O.C64, prm)
+    assert full.flags[11].mean() < 0.01
+    r = O.integrated_block(z, O.C64, prm)
+    assert r.channel_flags.nonzero()[0].tolist() == [11]
+
+
+def test_integrated_int_and_float_agree_on_integer_power():
+    rng = np.random.default_rng(5)
+    x = synth.ci8_block(rng, 24, 700)
+    p = O.power(x, O.CI8)
+    a = O.integrated_block(x, O.CI8)
+    b = O.integrated_block(p.astype(np.float32), O.F32)
+    assert (a.flags == b.flags).all()
+
+
+def test_series_stddev_exact_beyond_64_bits():
+    v = np.array([2 ** 33 - 1, 2 ** 33 - 5, 3, 2 ** 32], dtype=np.int64)
+    vals = [int(a) for a in v]
+    mu = Fraction(sum(vals), 4)
+    var = Fraction(sum(a * a for a in vals), 4) - mu * mu
+    assert O.series_stddev(v, True) == pytest.approx(math.sqrt(float(var)), rel=1e-15)
