@@ -78,6 +78,20 @@ typedef enum {
                                             along time, then along frequency on the time
                                             result; default: the scale-invariant rank
                                             operator the section cites                 */
+#define LOF_OPT_INTEGRATED 0x20u         /* integrated pre-correlation mode (Sec. 4): per
+                                            block, integrate time fully and flag the
+                                            spectrum along frequency (n_levels_freq
+                                            levels), then integrate the unflagged channels
+                                            fully and flag the time series along time
+                                            (n_levels levels); each series has its own
+                                            median, stddev and thresholds and gets the SIR
+                                            step; a flagged channel flags its row, a
+                                            flagged time its column; then the history
+                                            flagger as usual.  Blocks must have
+                                            n_times <= 16384 (LOF_ERR_INVALID).  The stats
+                                            entry holds the time series' median, stddev
+                                            and thresholds.  Complex int8 input stays
+                                            exact (64-bit sums, 128-bit moments).      */
 
 /* Phases of the path, in launch order (lof_phase_times) */
 #define LOF_PHASE_STATS 0        /* power, median, stddev, thresholds (Sec. 2.1, 4.2)   */
@@ -85,7 +99,10 @@ typedef enum {
 #define LOF_PHASE_ST_FREQ 2      /* SumThreshold along frequency (Sec. 2.1)             */
 #define LOF_PHASE_SIR_TIME 3     /* SIR operator along time (Sec. 2.2)                  */
 #define LOF_PHASE_SIR_FREQ 4     /* SIR operator along frequency (Sec. 2.2)             */
-#define LOF_PHASE_FINAL 5        /* history flagger (Sec. 4.1) and flag bytes           */
+#define LOF_PHASE_FINAL 5        /* history flagger (Sec. 4.1) and flag bytes; for blocks
+                                    of at most 64 channels and 4096 times (all blocks of
+                                    one input kind in the call) it also holds the SIR
+                                    operator, which then runs in the same kernel       */
 #define LOF_N_PHASES 6
 
 #define LOF_MAX_LEVELS 16
@@ -110,7 +127,10 @@ typedef struct {
   int32_t max_streams;         /* history stream ids are 0..max_streams-1             */
   int32_t max_channels;        /* ring capacity per stream; also the block C limit   */
   int32_t max_blocks_per_call;
-  int32_t _reserved0;
+  int32_t call_slots;          /* lof_flag_blocks calls that can be in flight before a
+                                  call waits on the host for the oldest: each slot
+                                  holds one call's descriptor table and scratch
+                                  (sized by the maxima above); 0 = 4              */
   int64_t max_samples_per_call;/* sum of C*T over one lof_flag_blocks call            */
   uint32_t options;            /* LOF_OPT_* bits                                      */
   int32_t _reserved1;

@@ -381,13 +381,18 @@ def series_stddev(v: np.ndarray, exact: bool) -> float:
     return math.sqrt(var)
 
 
+def series_thresholds(v: np.ndarray, params: Params, exact: bool, n_levels: int):
+    """(median, stddev, thresholds) of one integrated 1-D series (Sec. 2.1)."""
+    med = block_median(v)
+    sd = series_stddev(v, exact)
+    return med, sd, thresholds(med, sd, params, max(1, n_levels))
+
+
 def flag_series(v: np.ndarray, params: Params, exact: bool, n_levels: int) -> np.ndarray:
     """Flags of one integrated 1-D series: its own median and stddev, the
     thresholds of Sec. 2.1, one-dimensional SumThreshold, then the SIR step
     (Sec. 2.2) on the series' mask."""
-    med = block_median(v)
-    sd = series_stddev(v, exact)
-    th = thresholds(med, sd, params, max(1, n_levels))
+    _, _, th = series_thresholds(v, params, exact, n_levels)
     m = sumthreshold_rows(v[None, :], np.zeros((1, v.size), dtype=bool), th, n_levels, exact)
     if params.sir_eta_num > 0:
         op = sir_prose_rows if params.sir_prose else sir_rows

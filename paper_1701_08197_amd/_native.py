@@ -20,6 +20,7 @@ LOF_OPT_LITERAL_HISTORY_TIE = 0x2
 LOF_OPT_GRAPH = 0x4
 LOF_OPT_PHASE_TIMING = 0x8
 LOF_OPT_SIR_PROSE = 0x10
+LOF_OPT_INTEGRATED = 0x20
 # phases of lof_phase_times, in launch order
 PHASES = ("stats", "sumthreshold_time", "sumthreshold_freq", "sir_time", "sir_freq", "history_write")
 LOF_N_PHASES = len(PHASES)
@@ -46,7 +47,7 @@ class LofParams(ctypes.Structure):
         ("max_streams", ctypes.c_int32),
         ("max_channels", ctypes.c_int32),
         ("max_blocks_per_call", ctypes.c_int32),
-        ("_reserved0", ctypes.c_int32),
+        ("call_slots", ctypes.c_int32),
         ("max_samples_per_call", ctypes.c_int64),
         ("options", ctypes.c_uint32),
         ("_reserved1", ctypes.c_int32),

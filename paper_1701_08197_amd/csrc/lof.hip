@@ -25,6 +25,8 @@
 
 #include "lof.h"
 #include "lof_kernel_table.hpp"
+#include "lof_integrated.hpp"
+#include "lof_post.hpp"
 #include "lof_kernels.hpp"
 
 namespace lofk {
@@ -93,7 +95,8 @@ using lofk::DevParams;
 
 namespace {
 
-constexpr int NSLOT = 4;
+constexpr int NSLOT = 4;            // call slots when lof_params.call_slots is 0
+constexpr int MAX_SLOTS = 65536;
 constexpr int MAX_TIMES = lofk::SIR_SEG * lofk::SIR_MAX_SEGS;   // 262144
 
 thread_local const char* g_create_err = "no error";
@@ -129,7 +132,10 @@ bool lanes_allowed(int L, int bucket) {
 constexpr int NVAR = 6;   // time layouts: (integer, float) x (32, 48, 64 lanes)
 
 // kernels, for occupancy lookups
-enum KernId { K_STATS = 0, K_TIME = 2, K_FREQ = 8, K_SIRT = 10, K_SIRF = 13, K_FINAL = 14, K_PROSE = 16, NKERN = 18 };
+enum KernId {
+  K_STATS = 0, K_TIME = 2, K_FREQ = 8, K_SIRT = 10, K_SIRF = 13, K_FINAL = 14, K_PROSE = 16, K_INTEG = 18, K_POST = 20,
+  NKERN = 22
+};
 int variant_lanes(int v) { return v % 3 == 0 ? 32 : (v % 3 == 1 ? 48 : 64); }
 
 size_t elem_size(int dtype) { return dtype == LOF_CI8 ? 2 : (dtype == LOF_F32 ? 4 : 8); }
@@ -144,7 +150,7 @@ struct lof_ctx {
   int32_t* rhead = nullptr;
   double* pend = nullptr;
   uint8_t* pvalid = nullptr;
-  Slot slot[NSLOT];
+  std::vector<Slot> slot;         // call slots (descriptor table, scratch, event), used in turn
   int next = 0;
   lof_tuning tune;
   int occ[NKERN] = {};   // resident workgroups per CU of each kernel
@@ -196,6 +202,8 @@ DevParams dev_params(const lof_ctx* c, uint64_t* mask, uint64_t* mask2, BlockSta
   P.maxC = c->prm.max_channels;
   P.literal = (c->prm.options & LOF_OPT_LITERAL_HISTORY_TIE) ? 1 : 0;
   P.prose = (c->prm.options & LOF_OPT_SIR_PROSE) ? 1 : 0;
+  P.integrated = (c->prm.options & LOF_OPT_INTEGRATED) ? 1 : 0;
+  P.integ_tmax = 0;
   P._pad = 0;
   P.ring = c->ring;
   P.rcount = c->rcount;
@@ -225,6 +233,7 @@ const char* check_params(const lof_params* p) {
   if (p->max_channels < 1 || p->max_channels > LOF_MAX_CHANNELS) return "max_channels must be in 1..1024";
   if (p->max_blocks_per_call < 1) return "max_blocks_per_call must be >= 1";
   if (p->max_samples_per_call < 1) return "max_samples_per_call must be >= 1";
+  if (p->call_slots < 0 || p->call_slots > MAX_SLOTS) return "call_slots must be in 0..65536";
   return nullptr;
 }
 
@@ -245,6 +254,8 @@ const void* kernel_of(int k) {
   if (k >= K_SIRT && k < K_SIRT + 3) return lofk::kernel_sir_time(variant_lanes(k - K_SIRT));
   if (k == K_SIRF) return lofk::kernel_sir_freq();
   if (k == K_PROSE || k == K_PROSE + 1) return lofk::kernel_prose(k == K_PROSE + 1);
+  if (k == K_INTEG || k == K_INTEG + 1) return lofk::kernel_integrated(k == K_INTEG);
+  if (k == K_POST || k == K_POST + 1) return lofk::kernel_post(k == K_POST);
   return lofk::kernel_final(k == K_FINAL);
 }
 
@@ -344,6 +355,9 @@ lof_status validate(lof_ctx* c, const lof_block* blocks, int32_t n, bool check_i
   }
   if (samples > c->prm.max_samples_per_call)
     return fail(c, LOF_ERR_CAPACITY, "more samples than max_samples_per_call");
+  if (c->prm.options & LOF_OPT_INTEGRATED)
+    for (int i = 0; i < n; ++i)
+      if (blocks[i].n_times > lofk::INTEG_MAX_T) return fail(c, LOF_ERR_INVALID, "integrated mode: n_times > 16384");
   if (words > c->mask_words) return fail(c, LOF_ERR_CAPACITY, "mask scratch too small");
   return LOF_OK;
 }
@@ -387,7 +401,7 @@ void build_table(int* order, const lof_tuning& t, const lof_block* blocks, int32
 
 // one kernel launch over nb blocks (maxch > 0: chunked kernel, nb * maxch items)
 void launch(lof_ctx* c, const lof_tuning& t, int kid, int phase, const DevBlock* dd, int nb, int maxch, Slot& s,
-            int& ncounter, hipStream_t st, const DevParams& P) {
+            int& ncounter, hipStream_t st, const DevParams& P, size_t lds = 0) {
   const int items = maxch > 0 ? nb * maxch : nb;
   if (items <= 0) return;
   int* counter = nullptr;
@@ -402,7 +416,7 @@ void launch(lof_ctx* c, const lof_tuning& t, int kid, int phase, const DevBlock*
   DevParams a_p = P;
   if (maxch > 0) {
     void* args[] = {&a_blocks, &a_nb, &a_maxch, &a_counter, &a_p};
-    (void)hipLaunchKernel(kernel_of(kid), dim3(grid), dim3(lofk::WG), args, 0, st);
+    (void)hipLaunchKernel(kernel_of(kid), dim3(grid), dim3(lofk::WG), args, lds, st);
   } else {
     void* args[] = {&a_blocks, &a_nb, &a_counter, &a_p};
     (void)hipLaunchKernel(kernel_of(kid), dim3(grid), dim3(lofk::WG), args, 0, st);
@@ -436,6 +450,16 @@ void enqueue(lof_ctx* c, const lof_tuning& t, Slot& s, const int* counts, int n,
     const bool integer = kind == 0;
     const DevBlock* dk = s.d_desc + off;
     const DevBlock* hk = s.h_desc + off;
+    if (P.integrated) {
+      // spectrum and time series flagging per block, then history and flag bytes
+      DevParams Pi = P;
+      Pi.integ_tmax = max_chunks(hk, kcnt, [&](const DevBlock& b) { return b.T; });
+      launch(c, t, K_INTEG + kind, LOF_PHASE_STATS, dk, kcnt, 1, s, nc, st, Pi, lofk::integ_lds_bytes(Pi.integ_tmax));
+      const int mw = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::final_chunks(b.C); });
+      launch(c, t, K_FINAL + kind, LOF_PHASE_FINAL, dk, kcnt, mw, s, nc, st, P);
+      off += kcnt;
+      continue;
+    }
     launch(c, t, K_STATS + kind, LOF_PHASE_STATS, dk, kcnt, 0, s, nc, st, P);
     int mt[3] = {0, 0, 0};
     for (int j = 0, voff = 0; j < 3; voff += counts[3 * kind + j], ++j) {
@@ -447,6 +471,15 @@ void enqueue(lof_ctx* c, const lof_tuning& t, Slot& s, const int* counts, int n,
     }
     const int mf = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::freq_chunks(integer, b.C, b.T); });
     launch(c, t, K_FREQ + kind, LOF_PHASE_ST_FREQ, dk, kcnt, mf, s, nc, st, P);
+    // blocks of at most 64 channels and 4096 times: SIR, history and flag bytes in
+    // one kernel per block with the mask in LDS
+    bool post = !P.prose;
+    for (int i = 0; post && i < kcnt; ++i) post = lofk::post_eligible(hk[i].C, hk[i].T);
+    if (post) {
+      launch(c, t, K_POST + kind, LOF_PHASE_FINAL, dk, kcnt, 1, s, nc, st, P);
+      off += kcnt;
+      continue;
+    }
     if (c->prm.sir_eta_num > 0 && P.prose) {
       const int mr = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::prose_time_chunks(b.C); });
       launch(c, t, K_PROSE, LOF_PHASE_SIR_TIME, dk, kcnt, mr, s, nc, st, P);
@@ -568,7 +601,8 @@ lof_status lof_create(const lof_params* params, int hip_device, lof_ctx** out) {
                   (size_t)params->max_blocks_per_call * (size_t)params->max_channels + 64;
   const bool timing = (params->options & LOF_OPT_PHASE_TIMING) && !(params->options & LOF_OPT_GRAPH);
   const bool prose = (params->options & LOF_OPT_SIR_PROSE) != 0;
-  for (int i = 0; ok && i < NSLOT; ++i)
+  c->slot.resize(params->call_slots > 0 ? params->call_slots : NSLOT);
+  for (size_t i = 0; ok && i < c->slot.size(); ++i)
     ok = alloc_slot(c->slot[i], params->max_blocks_per_call, params->max_channels, c->mask_words, timing, prose);
   if (ok && (params->options & LOF_OPT_GRAPH)) {
     ok = alloc_slot(c->gslot, params->max_blocks_per_call, params->max_channels, c->mask_words, false, prose) &&
@@ -578,8 +612,13 @@ lof_status lof_create(const lof_params* params, int hip_device, lof_ctx** out) {
     hipDeviceProp_t prop;
     ok = hipGetDeviceProperties(&prop, hip_device) == hipSuccess;
     c->n_cu = ok ? prop.multiProcessorCount : 0;
+    const int integ_lds = (int)lofk::integ_lds_bytes(lofk::INTEG_MAX_T);
+    for (int k = K_INTEG; ok && k < K_INTEG + 2; ++k)
+      ok = hipFuncSetAttribute(kernel_of(k), hipFuncAttributeMaxDynamicSharedMemorySize, integ_lds) == hipSuccess;
     for (int k = 0; ok && k < NKERN; ++k)
-      ok = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c->occ[k], kernel_of(k), lofk::WG, 0) == hipSuccess;
+      ok = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c->occ[k], kernel_of(k), lofk::WG,
+                                                        (k == K_INTEG || k == K_INTEG + 1) ? 3072 * 8 : 0) ==
+           hipSuccess;
   }
   if (ok) ok = hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
@@ -645,7 +684,7 @@ lof_status lof_flag_blocks(lof_ctx* c, const lof_block* blocks, int32_t n, void*
   }
 
   Slot& s = c->slot[c->next];
-  c->next = (c->next + 1) % NSLOT;
+  c->next = (c->next + 1) % (int)c->slot.size();
   if (s.used) {
     // the slot's previous call must be done before its table and scratch are reused
     if (hipEventSynchronize(s.ev) != hipSuccess) return fail(c, LOF_ERR_DEVICE, "hipEventSynchronize failed");
@@ -880,6 +919,8 @@ lof_status lof_flag_blocks_static(const lof_params* params, int hip_device, cons
     lof_status code;
     if (const char* m = check_block(blocks[i], LOF_MAX_CHANNELS, 1, &code)) return static_fail(code, m);
     if (blocks[i].stream_id != -1) return static_fail(LOF_ERR_INVALID, "no history here: stream_id must be -1");
+    if ((params->options & LOF_OPT_INTEGRATED) && blocks[i].n_times > lofk::INTEG_MAX_T)
+      return static_fail(LOF_ERR_INVALID, "integrated mode: n_times > 16384");
     maxC = std::max(maxC, blocks[i].n_channels);
     words += block_mask_words(blocks[i]);
   }

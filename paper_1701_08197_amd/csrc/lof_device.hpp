@@ -21,7 +21,10 @@
 // (bit i <-> position lane_in_group*L + i).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
+
+#include "lof.h"
 
 namespace lofk {
 
@@ -49,6 +52,12 @@ constexpr int SIR_MAX_SEGS = 64;
 constexpr int HBINS = 4096;        // radix-select digit: 12 bits
 constexpr int MAXC = 1024;
 constexpr int BIG = 1 << 30;
+
+// the caller's per-block statistics entry (struct lof_block_stats of lof.h)
+constexpr int STATS_BYTES = (int)sizeof(lof_block_stats);
+constexpr int STATS_NFLAG = (int)offsetof(lof_block_stats, n_flagged);
+constexpr int STATS_HROWS = (int)offsetof(lof_block_stats, history_flagged_rows);
+static_assert(offsetof(lof_block_stats, threshold) == 2 * sizeof(double), "stats layout");
 
 struct DevBlock {
   const void* data;
@@ -119,7 +128,10 @@ __host__ __device__ inline int prose_freq_chunks(int T) { return (((T + 63) >> 6
 struct DevParams {
   double start, p, sens, hs;
   int32_t nl_t, nl_f, eta_num, eta_den, H, Hmin, maxC, literal;
-  int32_t prose, _pad;   // prose: the range-extension reading of the SIR step
+  int32_t prose;         // the range-extension reading of the SIR step
+  int32_t integrated;    // integrated pre-correlation mode
+  int32_t integ_tmax;    // longest block of the call (integrated mode: LDS layout)
+  int32_t _pad;
   double* ring;          // [streams][maxC][H]
   int32_t* rcount;       // [streams][maxC]
   int32_t* rhead;        // [streams][maxC]

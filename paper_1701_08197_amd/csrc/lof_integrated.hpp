@@ -1,0 +1,612 @@
+// lof_integrated.hpp -- the integrated pre-correlation mode (gfx950).
+//
+// Sec. 4 (integration paragraph) of van Nieuwpoort, "Towards exascale real-time
+// RFI mitigation", arXiv 1701.08197: integrate time fully and flag the spectrum
+// along frequency first, then integrate the unflagged channels fully and flag
+// the time series along time; a flagged channel flags its row, a flagged time
+// its column.  Each series gets its own median, stddev and thresholds (Sec. 2.1),
+// one-dimensional SumThreshold and the SIR step (Sec. 2.2).  The history
+// flagger and the flag bytes follow in the final kernel, as for full-rate
+// flagging.
+//
+// One workgroup per block.  A single pass over the input builds the spectrum
+// (row sums) and the all-channel time series (column sums, each thread owning
+// its columns in registers); both stay in LDS.  The flagged channels are then
+// taken out of the series (exactly, by subtraction, for integer input; by a
+// second sum over the unflagged channels for float input), the series is
+// flagged, and the block's mask words are written.  Integer input stays exact:
+// sums in 64-bit integers, second moments in 128-bit integers with the
+// correctly rounded quotient, window tests against floor(c * T_k).
+#pragma once
+#include "lof_kernels.hpp"
+
+namespace lofk {
+
+constexpr int INTEG_MAX_T = 16384;         // time series held in LDS
+constexpr int INTEG_SEG = INTEG_MAX_T / WG;   // positions per thread in the series passes (32)
+
+// dynamic LDS of the integrated kernel for blocks of up to Tmax samples (the
+// value and mask areas also hold the spectrum, up to MAXC channels)
+__host__ __device__ inline size_t integ_lds_bytes(int Tmax) {
+  const size_t n = (size_t)(Tmax > MAXC ? Tmax : MAXC);
+  return n * 8 + (size_t)MAXC * 8 + (size_t)NW * 64 * 8 + (n / 64 + 2) * 8 + 17 * 8 + 1024 + 16 * 8 + 128 * 8 + 256;
+}
+
+struct IntegSm {
+  uint64_t* val;      // series values (u64 integers / double bits), up to Tmax
+  uint64_t* spec;     // spectrum, up to MAXC
+  uint64_t* part;     // [NW][64] per-wave row partial sums (float input)
+  uint64_t* mask;     // mask words of the series being flagged
+  uint64_t* cmask;    // channel mask words (17)
+  uint32_t* hist;     // 256 radix bins
+  double* T;          // thresholds (16)
+  int64_t* G;         // integer window thresholds of one level, by count 0..64 (+pad)
+  int64_t* red;       // block reduction scratch (32 x 8 B)
+};
+
+__device__ __forceinline__ IntegSm integ_carve(unsigned char* base, int Tmax) {
+  IntegSm s;
+  const size_t n = (size_t)(Tmax > MAXC ? Tmax : MAXC);
+  unsigned char* p = base;
+  s.val = (uint64_t*)p;  p += n * 8;
+  s.spec = (uint64_t*)p; p += (size_t)MAXC * 8;
+  s.part = (uint64_t*)p; p += (size_t)NW * 64 * 8;
+  s.mask = (uint64_t*)p; p += (n / 64 + 2) * 8;
+  s.cmask = (uint64_t*)p; p += 17 * 8;
+  s.hist = (uint32_t*)p; p += 1024;
+  s.T = (double*)p;      p += 16 * 8;
+  s.G = (int64_t*)p;     p += 128 * 8;
+  s.red = (int64_t*)p;
+  return s;
+}
+
+// ---------------------------------------------------------------- block reductions
+template <class F>
+__device__ __forceinline__ int64_t block_reduce_i64(int64_t x, int64_t* red, F&& op) {
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x = op(x, (int64_t)__shfl_xor((long long)x, d));
+  __syncthreads();
+  if (lane == 0) red[wv] = x;
+  __syncthreads();
+  int64_t r = red[0];
+  for (int w = 1; w < NW; ++w) r = op(r, red[w]);
+  __syncthreads();
+  return r;
+}
+
+// sum of doubles in a fixed order: lanes by a shuffle tree, waves in order
+__device__ __forceinline__ double block_sum_f64(double x, int64_t* red) {
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+  __syncthreads();
+  if (lane == 0) red[wv] = __double_as_longlong(x);
+  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < NW; ++w) r += __longlong_as_double(red[w]);
+  __syncthreads();
+  return r;
+}
+
+// scans over the threads of the workgroup, in thread order
+__device__ __forceinline__ int64_t block_scan_incl(int64_t x, int64_t* red) {
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t y = (int64_t)__shfl_up((long long)x, d);
+    if (lane >= d) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) red[wv] = x;
+  __syncthreads();
+  for (int w = 0; w < wv; ++w) x += red[w];
+  __syncthreads();
+  return x;
+}
+
+// min over the threads before this one (BIG for thread 0)
+__device__ __forceinline__ int block_scan_min_excl(int x, int64_t* red) {
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
+  int incl = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(incl, d);
+    if (lane >= d) incl = min(incl, y);
+  }
+  int excl = __shfl_up(incl, 1);
+  if (lane == 0) excl = BIG;
+  __syncthreads();
+  if (lane == 63) red[wv] = incl;
+  __syncthreads();
+  for (int w = 0; w < wv; ++w) excl = min(excl, (int)red[w]);
+  __syncthreads();
+  return excl;
+}
+
+// max over the threads after this one (-BIG for the last)
+__device__ __forceinline__ int block_scan_max_excl_rev(int x, int64_t* red) {
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
+  int incl = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_down(incl, d);
+    if (lane + d < 64) incl = max(incl, y);
+  }
+  int excl = __shfl_down(incl, 1);
+  if (lane == 63) excl = -BIG;
+  __syncthreads();
+  if (lane == 0) red[wv] = incl;
+  __syncthreads();
+  for (int w = wv + 1; w < NW; ++w) excl = max(excl, (int)red[w]);
+  __syncthreads();
+  return excl;
+}
+
+// ---------------------------------------------------------------- exact integer moments
+// correctly rounded (round to nearest even) value of the 128-bit integer hi:lo
+// divided by n (1 <= n < 2^32), as a double.  The dividend is first shifted left
+// by k bits so that the integer quotient has at least 55 significant bits; the
+// quotient's top 53 bits, the next bit and whether anything nonzero follows
+// (lower quotient bits or a remainder) give the rounding; the result is scaled
+// back by 2^-k.
+__device__ inline double u128_div_rn(uint64_t hi, uint64_t lo, uint64_t n) {
+  if (hi == 0 && lo == 0) return 0.0;
+  const int bl_s = hi ? 128 - __builtin_clzll(hi) : 64 - __builtin_clzll(lo);
+  const int bl_n = 64 - __builtin_clzll(n);
+  const int k = max(0, 56 + bl_n - bl_s);
+  // (hi:lo) << k, k <= 88 and bl_s + k <= 128
+  if (k >= 64) {
+    hi = lo << (k - 64);
+    lo = 0;
+  } else if (k > 0) {
+    hi = (hi << k) | (lo >> (64 - k));
+    lo <<= k;
+  }
+  // long division by n in 32-bit digits: 128-bit quotient qhi:qlo, remainder r
+  uint64_t q[4];
+  uint64_t r = 0;
+  const uint32_t w[4] = {(uint32_t)(hi >> 32), (uint32_t)hi, (uint32_t)(lo >> 32), (uint32_t)lo};
+  for (int i = 0; i < 4; ++i) {
+    const uint64_t cur = (r << 32) | w[i];
+    q[i] = cur / n;
+    r = cur % n;
+  }
+  const uint64_t qhi = (q[0] << 32) | q[1], qlo = (q[2] << 32) | q[3];
+  const int nbits = qhi ? 128 - __builtin_clzll(qhi) : 64 - __builtin_clzll(qlo);   // >= 55
+  const int sh = nbits - 53;                  // quotient bits below the significand (>= 2)
+  uint64_t mant, rest_hi, rest_lo;            // mant = q >> sh, rest = q mod 2^sh
+  if (sh >= 64) {
+    mant = qhi >> (sh - 64);
+    rest_hi = (sh > 64) ? (qhi & ((1ull << (sh - 64)) - 1)) : 0;
+    rest_lo = qlo;
+  } else {
+    mant = (qlo >> sh) | (qhi << (64 - sh));
+    rest_hi = 0;
+    rest_lo = qlo & ((1ull << sh) - 1);
+  }
+  // compare rest + r/n with half = 2^(sh-1)
+  bool above, equal;
+  if (sh - 1 >= 64) {
+    const uint64_t hb = 1ull << (sh - 1 - 64);
+    above = rest_hi > hb || (rest_hi == hb && (rest_lo != 0 || r != 0));
+    equal = rest_hi == hb && rest_lo == 0 && r == 0;
+  } else {
+    const uint64_t hb = 1ull << (sh - 1);
+    above = rest_hi != 0 || rest_lo > hb || (rest_lo == hb && r != 0);
+    equal = rest_hi == 0 && rest_lo == hb && r == 0;
+  }
+  if (above || (equal && (mant & 1))) ++mant;   // mant <= 2^53: exact in a double
+  return __builtin_ldexp((double)mant, sh - k);
+}
+
+// population stddev of the n series values in s.val, with the oracle's formula
+template <bool INT>
+__device__ double integ_stddev(const IntegSm& s, int n) {
+  const int tid = thread_id();
+  if constexpr (INT) {
+    unsigned __int128 s2 = 0;
+    uint64_t s1 = 0;
+    for (int i = tid; i < n; i += WG) {
+      const uint64_t v = s.val[i];
+      s1 += v;
+      s2 += (unsigned __int128)v * v;
+    }
+    const int64_t S1 = block_reduce_i64((int64_t)s1, s.red, [](int64_t a, int64_t b) { return a + b; });
+    // 128-bit sum: low and high words separately, the carries from the low words
+    // counted exactly (each thread's low word is < 2^64; sums of 512 of them need
+    // 73 bits, kept as a carry count)
+    const uint64_t lo = (uint64_t)s2, hi = (uint64_t)(s2 >> 64);
+    const uint64_t lo_lo = lo & 0xffffffffull, lo_hi = lo >> 32;
+    const int64_t A = block_reduce_i64((int64_t)lo_lo, s.red, [](int64_t a, int64_t b) { return a + b; });
+    const int64_t B = block_reduce_i64((int64_t)lo_hi, s.red, [](int64_t a, int64_t b) { return a + b; });
+    const int64_t Hs = block_reduce_i64((int64_t)hi, s.red, [](int64_t a, int64_t b) { return a + b; });
+    // S2 = Hs * 2^64 + B * 2^32 + A (A, B < 2^41)
+    const unsigned __int128 S2 = ((unsigned __int128)(uint64_t)Hs << 64) + ((unsigned __int128)(uint64_t)B << 32) +
+                                 (unsigned __int128)(uint64_t)A;
+    const double mu = (double)(uint64_t)S1 / (double)n;   // S1 < 2^53: one rounding
+    const double ex2 = u128_div_rn((uint64_t)(S2 >> 64), (uint64_t)S2, (uint64_t)n);
+    double var = ex2 - mu * mu;
+    if (var < 0.0) var = 0.0;
+    return __builtin_sqrt(var);
+  } else {
+    double a = 0.0, b = 0.0;
+    for (int i = tid; i < n; i += WG) {
+      const double v = __longlong_as_double((long long)s.val[i]);
+      a += v;
+      b += v * v;
+    }
+    const double S1 = block_sum_f64(a, s.red), S2 = block_sum_f64(b, s.red);
+    const double mu = S1 / (double)n, ex2 = S2 / (double)n;
+    double var = ex2 - mu * mu;
+    if (var < 0.0) var = 0.0;
+    return __builtin_sqrt(var);
+  }
+}
+
+// ---------------------------------------------------------------- median (radix select)
+// order-preserving 64-bit key of a series value
+template <bool INT>
+__device__ __forceinline__ uint64_t integ_key(uint64_t v) {
+  if constexpr (INT) return v;
+  return (v & 0x8000000000000000ull) ? ~v : (v | 0x8000000000000000ull);
+}
+template <bool INT>
+__device__ __forceinline__ double integ_key_value(uint64_t k) {
+  if constexpr (INT) return (double)k;
+  const uint64_t v = (k & 0x8000000000000000ull) ? (k ^ 0x8000000000000000ull) : ~k;
+  return __longlong_as_double((long long)v);
+}
+
+// the key of rank r (0-based) among the n values: 8 passes of 8-bit digits
+template <bool INT>
+__device__ uint64_t integ_select(const IntegSm& s, int n, uint32_t r) {
+  const int tid = thread_id(), lane = tid & 63;
+  uint64_t prefix = 0;
+  for (int pass = 0; pass < 8; ++pass) {
+    const int shift = 56 - 8 * pass;
+    for (int i = tid; i < 256; i += WG) s.hist[i] = 0u;
+    __syncthreads();
+    const uint64_t hmask = pass == 0 ? 0ull : (~0ull << (shift + 8));
+    for (int i = tid; i < n; i += WG) {
+      const uint64_t k = integ_key<INT>(s.val[i]);
+      if ((k & hmask) == prefix) atomicAdd(&s.hist[(k >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    // the digit holding rank r: the first wave scans the 256 bins (4 per lane)
+    if (tid < 64) {
+      uint32_t c[4], sum = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        c[j] = s.hist[4 * lane + j];
+        sum += c[j];
+      }
+      uint32_t x = sum;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+      }
+      uint32_t before = x - sum;
+      if (r >= before && r < x) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (r >= before && r < before + c[j]) {
+            s.red[16] = 4 * lane + j;
+            s.red[17] = (int64_t)(r - before);
+          }
+          before += c[j];
+        }
+      }
+    }
+    __syncthreads();
+    prefix |= (uint64_t)s.red[16] << shift;
+    r = (uint32_t)s.red[17];
+    __syncthreads();
+  }
+  return prefix;
+}
+
+// ---------------------------------------------------------------- 1-D SumThreshold + SIR
+// Flags the n values in s.val (mask words in s.mask, which start cleared):
+// median, stddev and thresholds of the series, nl SumThreshold levels with
+// windows of I = 2^k <= n (level-synchronous, flagged samples out of sum and
+// count), then the SIR step.  Thread t takes the positions [t*SEG, t*SEG + SEG).
+template <bool INT>
+__device__ void integ_flag_series(const IntegSm& s, int n, int nl, const DevParams& P, double* med_out,
+                                  double* sd_out) {
+  const int tid = thread_id();
+  const int nw = (n + 63) >> 6;
+  for (int i = tid; i < nw; i += WG) s.mask[i] = 0ull;
+  // median (numpy definition) and stddev
+  const uint32_t r0 = (uint32_t)((n - 1) / 2), r1 = (uint32_t)(n / 2);
+  const uint64_t k0 = integ_select<INT>(s, n, r0);
+  const uint64_t k1 = (r1 == r0) ? k0 : integ_select<INT>(s, n, r1);
+  const double v0 = integ_key_value<INT>(k0), v1 = integ_key_value<INT>(k1);
+  const double med = (n & 1) ? v0 : (v0 + v1) / 2.0;
+  const double sd = integ_stddev<INT>(s, n);
+  if (tid == 0) {
+    double pk = 1.0;
+    for (int k = 0; k < 16; ++k) {
+      if (k < max(1, nl)) {
+        const double f = P.start * pk / (double)(1 << k);
+        s.T[k] = med + sd * (f * P.sens);
+        pk = pk * P.p;
+      } else {
+        s.T[k] = 0.0;
+      }
+    }
+  }
+  *med_out = med;
+  *sd_out = sd;
+  __syncthreads();
+  const int a = tid * INTEG_SEG;
+  for (int k = 0; k < nl && k < ST_MAX_LEVELS; ++k) {
+    const int I = 1 << k;
+    if (I > n) break;
+    const double Tk = s.T[k];
+    if (INT) {
+      // exact window thresholds floor(c * T_k) for c = 0..I (FMA-exact floor)
+      for (int c = tid; c <= I; c += WG) {
+        const double cd = (double)c, prod = cd * Tk, err = __builtin_fma(cd, Tk, -prod);
+        double fl = __builtin_floor(prod);
+        if (prod == fl && err < 0.0) fl -= 1.0;
+        s.G[c] = fl >= 9.0e18 ? INT64_MAX : (fl <= -9.0e18 ? INT64_MIN : (int64_t)fl);
+      }
+      __syncthreads();
+    }
+    // windows starting in this thread's positions: running sum and count
+    uint32_t hits = 0;
+    const int s_end = min(a + INTEG_SEG, n - I + 1);
+    if (a < s_end) {
+      int64_t Si = 0;
+      double Sf = 0.0;
+      int cnt = 0;
+      for (int j = a; j < a + I; ++j) {
+        const bool fl = (s.mask[j >> 6] >> (j & 63)) & 1ull;
+        if (!fl) {
+          ++cnt;
+          if (INT) Si += (int64_t)s.val[j];
+          else Sf += __longlong_as_double((long long)s.val[j]);
+        }
+      }
+      for (int st = a; st < s_end; ++st) {
+        if (st > a) {
+          const int out = st - 1, in = st + I - 1;
+          if (!((s.mask[out >> 6] >> (out & 63)) & 1ull)) {
+            --cnt;
+            if (INT) Si -= (int64_t)s.val[out];
+            else Sf -= __longlong_as_double((long long)s.val[out]);
+          }
+          if (!((s.mask[in >> 6] >> (in & 63)) & 1ull)) {
+            ++cnt;
+            if (INT) Si += (int64_t)s.val[in];
+            else Sf += __longlong_as_double((long long)s.val[in]);
+          }
+        }
+        bool h;
+        if (INT) h = cnt > 0 && Si > s.G[cnt];
+        else h = cnt > 0 && Sf > (double)cnt * Tk;
+        if (h) hits |= 1u << (st - a);
+      }
+    }
+    __syncthreads();   // every window of the level judged on the previous mask
+    while (hits) {
+      const int j = __builtin_ctz(hits);
+      hits &= hits - 1;
+      const int st = a + j;
+      // positions [st, st + I): at most two mask words
+      const int w0 = st >> 6, b0 = st & 63;
+      const uint64_t m0 = (b0 + I >= 64) ? (~0ull << b0) : (lowmask(I) << b0);
+      uint32_t* h32 = reinterpret_cast<uint32_t*>(s.mask);
+      if ((uint32_t)m0) atomicOr(&h32[2 * w0], (uint32_t)m0);
+      if ((uint32_t)(m0 >> 32)) atomicOr(&h32[2 * w0 + 1], (uint32_t)(m0 >> 32));
+      if (b0 + I > 64) {
+        const uint64_t m1 = lowmask(b0 + I - 64);
+        if ((uint32_t)m1) atomicOr(&h32[2 * w0 + 2], (uint32_t)m1);
+        if ((uint32_t)(m1 >> 32)) atomicOr(&h32[2 * w0 + 3], (uint32_t)(m1 >> 32));
+      }
+    }
+    __syncthreads();
+  }
+  // SIR step on the series mask
+  if (P.eta_num > 0) {
+    if (P.prose) {
+      // forward and backward scans by one thread over the words
+      if (tid == 0) {
+        const FastDiv fd((uint32_t)P.eta_den);
+        ProseScan f{0u, 0};
+        uint64_t* out = s.val;   // the values are no longer needed: reuse as output words
+        for (int w = 0; w < nw; ++w) {
+          const int nb = min(64, n - 64 * w);
+          out[w] = prose_fwd_word(s.mask[w] & lowmask(nb), 64 * w, nb, f, (uint32_t)P.eta_num, fd);
+        }
+        ProseScan r{0u, n};
+        for (int w = nw - 1; w >= 0; --w) {
+          const int nb = min(64, n - 64 * w);
+          const uint64_t x = s.mask[w] & lowmask(nb);
+          s.mask[w] = out[w] | prose_bwd_word(x, 64 * w, nb, r, (uint32_t)P.eta_num, fd);
+        }
+      }
+      __syncthreads();
+    } else {
+      // linear form, INTEG_SEG positions per thread, block scans between threads
+      const int num = P.eta_num, den = P.eta_den;
+      const int nval = clampi(n - a, 0, INTEG_SEG);
+      const uint64_t bits = nval > 0 ? ((s.mask[a >> 6] >> (a & 63)) & lowmask(nval)) : 0ull;
+      const SirSum ss = sir_lane_summary<INTEG_SEG>(bits, nval, num, den);
+      // exclusive prefix sum of the totals, prefix min of base + mn, suffix max of base + mx
+      const int64_t tot_incl = block_scan_incl(ss.tot, s.red);
+      const int base = (int)(tot_incl - ss.tot);
+      const int pm = block_scan_min_excl(nval > 0 ? base + ss.mn : BIG, s.red);
+      const int sx = block_scan_max_excl_rev(nval > 0 ? base + ss.mx : -BIG, s.red);
+      const uint64_t out = sir_lane_apply<INTEG_SEG>(bits, nval, num, den, base, pm, sx);
+      __syncthreads();
+      if (nval > 0) {
+        uint32_t* h32 = reinterpret_cast<uint32_t*>(s.mask);
+        const uint64_t sh = out << (a & 63);   // INTEG_SEG = 32: inside one word
+        if ((uint32_t)sh) atomicOr(&h32[2 * (a >> 6)], (uint32_t)sh);
+        if ((uint32_t)(sh >> 32)) atomicOr(&h32[2 * (a >> 6) + 1], (uint32_t)(sh >> 32));
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------- the block
+// powers of 8 consecutive samples of a row from t0 (zero past the row's end)
+template <bool INT>
+__device__ __forceinline__ void integ_load8(const DevBlock& b, int row, int t0, typename PowT<INT>::T (&v)[8]) {
+  if (b.aligned && t0 + 8 <= b.T) load8v<INT>(b, row, t0, v);
+  else load8<INT>(b, row, t0, v);
+}
+
+template <bool INT>
+__device__ void phase_integrated(const DevBlock& b, const DevParams& P, const IntegSm& s) {
+  typedef typename PowT<INT>::T VT;
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
+  const int C = b.C, T = b.T, W = (T + 63) >> 6;
+  const int nq = (T + 8 * WG - 1) / (8 * WG);   // chunks of 8 columns per thread (<= 4)
+  for (int i = tid; i < C; i += WG) s.spec[i] = 0ull;
+  for (int i = tid; i < 17; i += WG) s.cmask[i] = 0ull;
+  __syncthreads();
+  // one pass: column sums in registers (each thread owns its columns), row sums
+  // by a wave reduction per row (exact integer atomics, or per-wave partials
+  // added in wave order for float input)
+  uint64_t ci[4][8];
+  double cf[4][8];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      ci[q][j] = 0ull;
+      cf[q][j] = 0.0;
+    }
+  for (int r0 = 0; r0 < C; r0 += 64) {
+    const int r1 = min(C, r0 + 64);
+    for (int row = r0; row < r1; ++row) {
+      uint64_t rs_i = 0;
+      double rs_f = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int t0 = (tid + q * WG) * 8;
+        if (q < nq && t0 < T) {
+          VT v[8];
+          integ_load8<INT>(b, row, t0, v);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            if (INT) {
+              ci[q][j] += (uint64_t)v[j];
+              rs_i += (uint64_t)v[j];
+            } else {
+              cf[q][j] += (double)v[j];
+              rs_f += (double)v[j];
+            }
+          }
+        }
+      }
+      if (INT) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) rs_i += (uint64_t)__shfl_xor((long long)rs_i, d);
+        if (lane == 0 && rs_i) atomicAdd((unsigned long long*)&s.spec[row], (unsigned long long)rs_i);
+      } else {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) rs_f += __shfl_xor(rs_f, d);
+        if (lane == 0) s.part[wv * 64 + (row - r0)] = (uint64_t)__double_as_longlong(rs_f);
+      }
+    }
+    if (!INT) {
+      __syncthreads();
+      for (int row = r0 + tid; row < r1; row += WG) {
+        double acc = 0.0;
+        for (int w = 0; w < NW; ++w) acc += __longlong_as_double((long long)s.part[w * 64 + (row - r0)]);
+        s.spec[row] = (uint64_t)__double_as_longlong(acc);
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  // spectrum: flag along frequency first
+  for (int i = tid; i < C; i += WG) s.val[i] = s.spec[i];
+  __syncthreads();
+  double med, sd;
+  integ_flag_series<INT>(s, C, min(P.nl_f, ST_MAX_LEVELS), P, &med, &sd);
+  for (int i = tid; i < (C + 63) / 64; i += WG) s.cmask[i] = s.mask[i];
+  if (INT) {
+    // the rows' exact power sums, for the history flagger
+    for (int i = tid; i < C; i += WG) gp<uint64_t>(P.rowsum)[(int64_t)b.sidx * P.maxC + i] = s.spec[i];
+  }
+  __syncthreads();
+  // the time series of the unflagged channels
+  int nflag = 0;
+  for (int i = 0; i < (C + 63) / 64; ++i) nflag += __popcll(s.cmask[i]);
+  if (INT) {
+    // subtract the flagged rows from the all-channel column sums (exact)
+    for (int w = 0; w < (C + 63) / 64; ++w) {
+      uint64_t m = s.cmask[w];
+      while (m) {
+        const int row = 64 * w + __builtin_ctzll(m);
+        m &= m - 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int t0 = (tid + q * WG) * 8;
+          if (q < nq && t0 < T) {
+            VT v[8];
+            integ_load8<INT>(b, row, t0, v);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) ci[q][j] -= (uint64_t)v[j];
+          }
+        }
+      }
+    }
+  } else if (nflag > 0) {
+    // float input: the sums over the unflagged channels again, in row order
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) cf[q][j] = 0.0;
+    for (int row = 0; row < C; ++row) {
+      if ((s.cmask[row >> 6] >> (row & 63)) & 1ull) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int t0 = (tid + q * WG) * 8;
+        if (q < nq && t0 < T) {
+          VT v[8];
+          integ_load8<INT>(b, row, t0, v);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) cf[q][j] += (double)v[j];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int t0 = (tid + q * WG) * 8;
+    if (q < nq && t0 < T) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (t0 + j < T) s.val[t0 + j] = INT ? ci[q][j] : (uint64_t)__double_as_longlong(cf[q][j]);
+    }
+  }
+  __syncthreads();
+  integ_flag_series<INT>(s, T, min(P.nl_t, ST_MAX_LEVELS), P, &med, &sd);
+  // the block's mask words: a flagged channel's whole row, else the time flags
+  GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
+  for (int i = tid; i < C * W; i += WG) {
+    const int row = i / W, w = i - row * W;
+    const uint64_t valid = lowmask(min(64, T - 64 * w));
+    const bool chan = (s.cmask[row >> 6] >> (row & 63)) & 1ull;
+    m0[(int64_t)row * W + w] = chan ? valid : (s.mask[w] & valid);
+  }
+  // statistics entry: the time series' median, stddev and thresholds; the flag
+  // totals are accumulated by the final kernel
+  if (P.stats && tid < STATS_BYTES / 8) {
+    GLB double* st = (GLB double*)(gp<char>(P.stats) + (int64_t)b.out_idx * STATS_BYTES);
+    if (tid == 0) st[0] = med;
+    else if (tid == 1) st[1] = sd;
+    else if (tid < 2 + LOF_MAX_LEVELS) st[tid] = s.T[tid - 2];
+    else *(GLB long long*)(st + tid) = 0;
+  }
+}
+
+}  // namespace lofk

@@ -11,4 +11,6 @@ const void* kernel_sir_time(int lanes);
 const void* kernel_sir_freq();
 const void* kernel_final(bool integer);
 const void* kernel_prose(bool freq);                // prose SIR reading: rows / columns
+const void* kernel_integrated(bool integer);        // integrated pre-correlation mode
+const void* kernel_post(bool integer);              // SIR + history + bytes, mask in LDS
 }  // namespace lofk

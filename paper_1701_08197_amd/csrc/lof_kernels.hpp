@@ -1736,8 +1736,8 @@ __device__ __forceinline__ void phase_sir_freq_col(const DevBlock& b, const DevP
     unsigned long long nfl = lane < C ? (unsigned long long)__popcll(fw) : 0ull;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) nfl += __shfl_xor(nfl, d);
-    char* st = (char*)P.stats + (int64_t)b.out_idx * (int64_t)(18 * 8 + 16);
-    if (lane == 0 && nfl) atomicAdd((unsigned long long*)(st + 18 * 8), nfl);
+    char* st = (char*)P.stats + (int64_t)b.out_idx * STATS_BYTES;
+    if (lane == 0 && nfl) atomicAdd((unsigned long long*)(st + STATS_NFLAG), nfl);
   }
 }
 
@@ -1755,12 +1755,12 @@ __device__ __forceinline__ void phase_sir_freq(const DevBlock& b, const DevParam
 // stddev of the committed means.  One wave per row; the ring's state does not
 // depend on this block, so its loads are issued first and overlap the loads of
 // the row's mask and samples.
-template <bool INT>
-__device__ __forceinline__ void row_unflagged(const DevBlock& b, const DevParams& P, int row, int lane,
-                                              uint64_t rowsum, double& usum, int& cnt) {
+// mrow: the row's mask words (global memory or LDS)
+template <bool INT, class MP>
+__device__ __forceinline__ void row_unflagged(const DevBlock& b, MP mrow, int row, int lane, uint64_t rowsum,
+                                              double& usum, int& cnt) {
   const int T = b.T;
   const int W = (T + 63) >> 6;
-  const GLB uint64_t* mrow = gp<uint64_t>(P.maskw) + b.mask_off + (int64_t)row * W;
   if constexpr (INT) {
     // the row's power sum (exact, from the time pass) minus the flagged
     // samples' power: input is read only for mask words with flags
@@ -1770,7 +1770,7 @@ __device__ __forceinline__ void row_unflagged(const DevBlock& b, const DevParams
     for (int wi = lane; wi < W; wi += 64) {
       const int t0 = wi * 64;
       const int nv = min(64, T - t0);
-      const uint64_t fw = ld_mask(mrow + wi) & lowmask(nv);
+      const uint64_t fw = mrow[wi] & lowmask(nv);
       nf += __popcll(fw);
       if (fw == 0) continue;
       const GLB uint8_t* rb = rbase + (int64_t)t0 * 2;
@@ -1810,7 +1810,7 @@ __device__ __forceinline__ void row_unflagged(const DevBlock& b, const DevParams
     const bool fast = b.aligned && (T & 7) == 0;
     for (int ci = lane; ci < nch; ci += 64) {
       const int t0 = ci * 8;
-      const uint32_t fb = (uint32_t)(ld_mask(mrow + (t0 >> 6)) >> (t0 & 63)) & 0xffu;
+      const uint32_t fb = (uint32_t)(mrow[t0 >> 6] >> (t0 & 63)) & 0xffu;
       float v[8];
       int nv = 8;
       if (fast) load8v<false>(b, row, t0, v);
@@ -1833,6 +1833,68 @@ __device__ __forceinline__ void row_unflagged(const DevBlock& b, const DevParams
   }
 }
 
+// The history decision of one row (one wave): the row's current mean (usum /
+// cnt over its unflagged samples) against mean + history_sensitivity * stddev of
+// the committed ring (L entries, head = next write slot; lane j holds ring slot
+// j in xs when the ring fits one wave), sums in ring order as the sequential
+// definition has them; stages the pushed value and sets the row's bit in
+// rowflag (LDS) when it flags.
+__device__ __forceinline__ void history_judge(const DevParams& P, int64_t idx, int L, int head,
+                                              const GLB double* ring, double xs, bool small_ring, double usum,
+                                              int cnt, int lane, uint32_t* rowflag, int row) {
+  const bool judge = L >= P.Hmin;
+  // the first 64 entries in ring order, oldest first (lane j holds entry j)
+  int k0 = head - L + lane;
+  if (k0 < 0) k0 += P.H;
+  const int ks = (lane < L) ? k0 : 0;
+  const double xr = small_ring ? __shfl(xs, ks) : ((judge && lane < L) ? ring[k0] : 0.0);
+  const double x0 = (judge && lane < L) ? xr : 0.0;
+  if (cnt == 0) {
+    if (lane == 0) gp<uint8_t>(P.pvalid)[idx] = 0;
+    return;
+  }
+  const double cur = usum / (double)cnt;
+  bool flag = false;
+  double pushv = cur;
+  if (judge) {
+    double acc = 0.0;
+    for (int j0 = 0; j0 < L; j0 += 64) {
+      double x = x0;
+      if (j0 > 0) {
+        int k = head - L + j0 + lane;
+        if (k < 0) k += P.H;
+        x = j0 + lane < L ? ring[k] : 0.0;
+      }
+      const int m = min(64, L - j0);
+      for (int q = 0; q < m; ++q) acc += lane_double(x, q);
+    }
+    const double hm = acc / (double)L;
+    acc = 0.0;
+    for (int j0 = 0; j0 < L; j0 += 64) {
+      double x = x0;
+      if (j0 > 0) {
+        int k = head - L + j0 + lane;
+        if (k < 0) k += P.H;
+        x = j0 + lane < L ? ring[k] : 0.0;
+      }
+      const int m = min(64, L - j0);
+      for (int q = 0; q < m; ++q) {
+        const double d = lane_double(x, q) - hm;
+        acc += d * d;
+      }
+    }
+    const double hv = acc / (double)L;
+    const double thr = hm + P.hs * __builtin_sqrt(hv);
+    flag = P.literal ? (cur >= thr) : (cur > thr);
+    if (flag) pushv = thr;
+  }
+  if (lane == 0) {
+    gp<double>(P.pend)[idx] = pushv;
+    gp<uint8_t>(P.pvalid)[idx] = 1;
+    if (flag) atomicOr(&rowflag[row >> 5], 1u << (row & 31));
+  }
+}
+
 template <bool INT, class SM>
 __device__ __forceinline__ void phase_history(const DevBlock& b, const DevParams& P, SM& sm, const int r0,
                                               const int r1) {
@@ -1851,62 +1913,12 @@ __device__ __forceinline__ void phase_history(const DevBlock& b, const DevParams
     const bool small_ring = P.H <= 64;
     const double xs = (small_ring && lane < P.H) ? ring[lane] : 0.0;
     const uint64_t rowsum = INT ? gp<const uint64_t>(P.rowsum)[(int64_t)b.sidx * P.maxC + row] : 0ull;
+    const int W = (b.T + 63) >> 6;
+    const GLB uint64_t* mrow = gp<uint64_t>(P.maskw) + b.mask_off + (int64_t)row * W;
     double usum;
     int cnt;
-    row_unflagged<INT>(b, P, row, lane, rowsum, usum, cnt);
-    const bool judge = L >= P.Hmin;
-    // the first 64 entries in ring order, oldest first (lane j holds entry j)
-    int k0 = head - L + lane;
-    if (k0 < 0) k0 += P.H;
-    const int ks = (lane < L) ? k0 : 0;
-    const double xr = small_ring ? __shfl(xs, ks) : ((judge && lane < L) ? ring[k0] : 0.0);
-    const double x0 = (judge && lane < L) ? xr : 0.0;
-    if (cnt == 0) {
-      if (lane == 0) gp<uint8_t>(P.pvalid)[idx] = 0;
-    } else {
-      const double cur = usum / (double)cnt;
-      bool flag = false;
-      double pushv = cur;
-      if (judge) {
-        // sums in ring order, one entry at a time over values read across
-        // lanes, as the sequential definition has them
-        double acc = 0.0;
-        for (int j0 = 0; j0 < L; j0 += 64) {
-          double x = x0;
-          if (j0 > 0) {
-            int k = head - L + j0 + lane;
-            if (k < 0) k += P.H;
-            x = j0 + lane < L ? ring[k] : 0.0;
-          }
-          const int m = min(64, L - j0);
-          for (int q = 0; q < m; ++q) acc += lane_double(x, q);
-        }
-        const double hm = acc / (double)L;
-        acc = 0.0;
-        for (int j0 = 0; j0 < L; j0 += 64) {
-          double x = x0;
-          if (j0 > 0) {
-            int k = head - L + j0 + lane;
-            if (k < 0) k += P.H;
-            x = j0 + lane < L ? ring[k] : 0.0;
-          }
-          const int m = min(64, L - j0);
-          for (int q = 0; q < m; ++q) {
-            const double d = lane_double(x, q) - hm;
-            acc += d * d;
-          }
-        }
-        const double hv = acc / (double)L;
-        const double thr = hm + P.hs * __builtin_sqrt(hv);
-        flag = P.literal ? (cur >= thr) : (cur > thr);
-        if (flag) pushv = thr;
-      }
-      if (lane == 0) {
-        gp<double>(P.pend)[idx] = pushv;
-        gp<uint8_t>(P.pvalid)[idx] = 1;
-        if (flag) atomicOr(&sm.rowflag[row >> 5], 1u << (row & 31));
-      }
-    }
+    row_unflagged<INT>(b, mrow, row, lane, rowsum, usum, cnt);
+    history_judge(P, idx, L, head, ring, xs, small_ring, usum, cnt, lane, sm.rowflag, row);
   }
   __syncthreads();
 }
@@ -1961,12 +1973,12 @@ __device__ __forceinline__ void phase_write(const DevBlock& b, const DevParams& 
   if (!P.stats) return;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) nfl += __shfl_xor(nfl, d);
-  char* st = (char*)P.stats + (int64_t)b.out_idx * (int64_t)(18 * 8 + 16);
-  if (lane == 0 && nfl) atomicAdd((unsigned long long*)(st + 18 * 8), nfl);
+  char* st = (char*)P.stats + (int64_t)b.out_idx * STATS_BYTES;
+  if (lane == 0 && nfl) atomicAdd((unsigned long long*)(st + STATS_NFLAG), nfl);
   if (tid == 0) {
     int hr = 0;
     for (int row = r0; row < r1; ++row) hr += (sm.rowflag[row >> 5] >> (row & 31)) & 1u;
-    if (hr) atomicAdd((int*)(st + 19 * 8), hr);
+    if (hr) atomicAdd((int*)(st + STATS_HROWS), hr);
   }
 }
 
@@ -2026,11 +2038,11 @@ __global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_stats_kernel(const D
       else if (k == 1) bs->sigma = sm.sigma;
       else bs->T[k - 2] = sm.T[k - 2];
     }
-    if (P.stats && k < 20) {
-      GLB double* st = (GLB double*)(gp<char>(P.stats) + (int64_t)b.out_idx * (int64_t)(18 * 8 + 16));
+    if (P.stats && k < STATS_BYTES / 8) {
+      GLB double* st = (GLB double*)(gp<char>(P.stats) + (int64_t)b.out_idx * STATS_BYTES);
       if (k == 0) st[0] = sm.median;
       else if (k == 1) st[1] = sm.sigma;
-      else if (k < 18) st[k] = sm.T[k - 2];
+      else if (k < 2 + LOF_MAX_LEVELS) st[k] = sm.T[k - 2];
       else *(GLB long long*)(st + k) = 0;   // flagged samples; history rows and padding
     }
   });
@@ -2088,7 +2100,7 @@ __global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_final_kernel(const D
     if (ch >= final_chunks(b.C)) return;
     const int r0 = ch * NW, r1 = min(b.C, r0 + NW);
     phase_history<INT>(b, P, sm, r0, r1);
-    phase_write(b, P, sm, r0, r1, sirf_writes_bytes(P.eta_num, P.prose, b.C));
+    phase_write(b, P, sm, r0, r1, sirf_writes_bytes(P.eta_num, P.prose | P.integrated, b.C));
   });
 }
 
