@@ -12,9 +12,14 @@ history stream sees its blocks in arrival order (Sec. 4.1: the history must be
 applied in time order even when seconds are processed on different workers).
 
 Inputs are flagged where they landed in device memory; the arena holds the flag
-outputs (and bounds how much work is admitted).  Descriptor tables are built
-with vectorised numpy writes into the lof_block layout.  All flagging work runs
-in the HIP library; this module only schedules.
+outputs (and bounds how much work is admitted).  A request's inputs may still be
+in flight on the producer's stream when it is submitted: submit() records an
+event on the caller's current stream and the flagging stream waits on it.
+Back-pressure: a request still waiting for admission `max_wait_s` after its
+arrival (e.g. one real-time deadline) is shed and counted instead of queueing
+without bound, so latency past saturation stays bounded.  Descriptor tables are
+built with vectorised numpy writes into the lof_block layout.  All flagging work
+runs in the HIP library; this module only schedules.
 """
 from __future__ import annotations
 
@@ -44,6 +49,8 @@ class Request:
     done: float = 0.0
     slots: list = field(default_factory=list)
     ptrs: np.ndarray = None
+    ready: object = None                # event on the producer's stream (inputs written)
+    admit_seq: int = -1                 # order of admission (debugging, tests)
 
     def __post_init__(self):
         self.ptrs = np.fromiter((t.data_ptr() for t in self.sources), dtype=np.uint64, count=len(self.sources))
@@ -53,7 +60,8 @@ class Service:
     """Continuous-batching flagger over a fixed device arena of `n_slots` blocks."""
 
     def __init__(self, n_stations: int, max_subbands: int, n_slots: int, C: int = 64, T: int = 3072,
-                 n_hip_streams: int = 2, keep_outputs: bool = False, device: int = 0, **param_overrides):
+                 n_hip_streams: int = 2, keep_outputs: bool = False, device: int = 0,
+                 max_wait_s: float | None = None, **param_overrides):
         import torch
         self.torch = torch
         self.C, self.T = C, T
@@ -82,23 +90,38 @@ class Service:
         self.completed: list = []
         self.keep_outputs = keep_outputs
         self.outputs: dict = {}             # (station, second, subband) -> host uint8 array
+        self.max_wait_s = max_wait_s
+        self.shed = 0                       # requests dropped by back-pressure
+        self.n_admitted = 0
 
     # ---------------------------------------------------------------- admission
     def submit(self, req: Request) -> None:
+        if len(req.sources) > self.n_slots:
+            raise ValueError(f"request needs {len(req.sources)} blocks, the arena has {self.n_slots}")
+        req.ready = self.torch.cuda.Event()
+        req.ready.record(self.torch.cuda.current_stream(self.dev))
         self.queue.append(req)
 
     def _admit(self) -> None:
         batch, need_free = [], 0
         waiting = collections.deque()
         stations_in_batch = set()
+        blocked = set()                     # stations with an earlier request still waiting
+        now = time.perf_counter()
         while self.queue:
             r = self.queue.popleft()
             n = len(r.sources)
-            if (r.station in self.busy_station or r.station in stations_in_batch
+            if self.max_wait_s is not None and now - r.arrival > self.max_wait_s:
+                self.shed += 1              # past its deadline before admission
+                continue
+            if (r.station in self.busy_station or r.station in stations_in_batch or r.station in blocked
                     or need_free + n > len(self.free)):
                 waiting.append(r)
+                blocked.add(r.station)      # its later seconds must not overtake it
                 continue
             batch.append(r)
+            r.admit_seq = self.n_admitted
+            self.n_admitted += 1
             stations_in_batch.add(r.station)
             need_free += n
         # keep arrival order of everything not admitted
@@ -117,6 +140,10 @@ class Service:
             tab["flags"][k:k + n] = self.out_ptr[r.slots]
             tab["sid"][k:k + n] = r.station * self.max_subbands + np.arange(n, dtype=np.int32)
             k += n
+        for r in batch:
+            s.wait_event(r.ready)
+            for t in r.sources:
+                t.record_stream(s)
         arr = ctypes.cast(tab.ctypes.data, ctypes.POINTER(N.LofBlock))
         rc = self.fl.flag_blocks_raw(arr, need_free, s.cuda_stream)
         if rc != 0:

@@ -64,3 +64,39 @@ def test_alone_equals_mixed():
                     assert (r.flags == mixed[(st, sec, sb)].astype(bool)).all(), (st, sec, sb)
                 h.commit()
         fl.close()
+
+
+def test_station_order_kept_when_subband_counts_change():
+    """A station whose subband count changes between seconds, with an arena
+    that is nearly full: its seconds are admitted in arrival order (a smaller
+    later second never overtakes a deferred earlier one), and every station's
+    flags equal a sequential run, history included."""
+    say("[station_order_kept_when_subband_counts_change]")
+    import torch
+    import paper_1701_08197_amd as P
+    from paper_1701_08197_amd.serve import Request, Service
+    counts = {0: [6, 1, 5, 1, 6], 1: [2, 2, 2, 2, 2], 2: [1, 6, 1, 6, 1]}
+    dev = {(st, sec, sb): torch.from_numpy(block(st, sec, sb)).cuda()
+           for st, per in counts.items() for sec, n in enumerate(per) for sb in range(n)}
+    arrivals = sorted((0.01 * sec + 0.001 * st, st, sec) for st, per in counts.items() for sec in range(len(per)))
+    hp = dict(history_len=4, history_min=2, history_sensitivity=3.0)
+    svc = Service(len(counts), 8, n_slots=7, C=C, T=T, keep_outputs=True, **hp)
+    with pytest.raises(ValueError):
+        svc.submit(Request(0, 99, 0.0, [dev[(0, 0, 0)]] * 8))
+    done = svc.run(arrivals, lambda st, sec: [dev[(st, sec, sb)] for sb in range(counts[st][sec])], speedup=1e4)
+    assert len(done) == len(arrivals) and svc.shed == 0
+    for st in counts:
+        seq = [r.admit_seq for r in sorted((r for r in done if r.station == st), key=lambda r: r.second)]
+        assert seq == sorted(seq), (st, seq)
+    mixed = svc.outputs
+    svc.close()
+    for st, per in counts.items():
+        fl = P.Flagger(P.default_params(max_streams=8, max_channels=C, max_blocks_per_call=8,
+                                        max_samples_per_call=8 * C * T, options=P.LOF_OPT_AUTOCOMMIT, **hp))
+        for sec, n in enumerate(per):
+            outs = [torch.zeros((C, T), dtype=torch.uint8, device="cuda") for _ in range(n)]
+            fl.flag_blocks([P.Block(dev[(st, sec, sb)], outs[sb], P.LOF_CI8, sb) for sb in range(n)])
+            torch.cuda.synchronize()
+            for sb in range(n):
+                assert (outs[sb].cpu().numpy() == mixed[(st, sec, sb)]).all(), (st, sec, sb)
+        fl.close()
