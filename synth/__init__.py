@@ -151,6 +151,29 @@ def ci8_block(rng: np.random.Generator, C: int, T: int, sigma: float = CFG1_SIGM
     return out
 
 
+def plan_mask(plan, C: int, T: int) -> dict:
+    """Boolean [C, T] masks of where each kind of interferer of an RFI plan was
+    injected (ground truth for quality reports)."""
+    out = {k: np.zeros((C, T), dtype=bool) for k in ("tone", "impulse", "burst")}
+    for kind, c0, c1, t0, t1, _, _ in plan:
+        out[kind][c0:c1, t0:t1] = True
+    return out
+
+
+def config1_truth(b: int, second: int = 0):
+    """(block, interferer masks, pulse mask) of config1_block(b, second): the same
+    draws, with the plan kept."""
+    subband = b % CFG1_SUBBANDS
+    idx = b if second == 0 else second * CFG1_STATIONS * CFG1_POLS * CFG1_SUBBANDS + b
+    rng = rng_for(1, idx)
+    C, T, sigma = CFG1_C, CFG1_T, CFG1_SIGMA
+    re = rng.standard_normal((C, T), dtype=np.float32) * np.float32(sigma)
+    im = rng.standard_normal((C, T), dtype=np.float32) * np.float32(sigma)
+    plan = rfi_plan(rng, C, T)
+    x = config1_block(b, second)
+    return x, plan_mask(plan, C, T), _pulse_profile(subband, C, T, t_start=second * CFG1_SECOND_S)
+
+
 def config1_index(station: int, pol: int, subband: int) -> int:
     return (station * CFG1_POLS + pol) * CFG1_SUBBANDS + subband
 
