@@ -200,15 +200,15 @@ __device__ inline double u128_div_rn(uint64_t hi, uint64_t lo, uint64_t n) {
   return __builtin_ldexp((double)mant, sh - k);
 }
 
-// population stddev of the n series values in s.val, with the oracle's formula
+// population stddev of the n series values in vals, with the oracle's formula
 template <bool INT>
-__device__ double integ_stddev(const IntegSm& s, int n) {
+__device__ double integ_stddev(const IntegSm& s, const uint64_t* vals, int n) {
   const int tid = thread_id();
   if constexpr (INT) {
     unsigned __int128 s2 = 0;
     uint64_t s1 = 0;
     for (int i = tid; i < n; i += WG) {
-      const uint64_t v = s.val[i];
+      const uint64_t v = vals[i];
       s1 += v;
       s2 += (unsigned __int128)v * v;
     }
@@ -232,7 +232,7 @@ __device__ double integ_stddev(const IntegSm& s, int n) {
   } else {
     double a = 0.0, b = 0.0;
     for (int i = tid; i < n; i += WG) {
-      const double v = __longlong_as_double((long long)s.val[i]);
+      const double v = __longlong_as_double((long long)vals[i]);
       a += v;
       b += v * v;
     }
@@ -258,18 +258,24 @@ __device__ __forceinline__ double integ_key_value(uint64_t k) {
   return __longlong_as_double((long long)v);
 }
 
-// the key of rank r (0-based) among the n values: 8 passes of 8-bit digits
+// the key of rank r (0-based) among the n values, by 8-bit digits from the most
+// significant byte in which the smallest and largest key differ (every key
+// shares the bytes above it); kmin / kmax are the extreme keys
 template <bool INT>
-__device__ uint64_t integ_select(const IntegSm& s, int n, uint32_t r) {
+__device__ uint64_t integ_select(const IntegSm& s, const uint64_t* vals, int n, uint32_t r, uint64_t kmin,
+                                 uint64_t kmax) {
   const int tid = thread_id(), lane = tid & 63;
-  uint64_t prefix = 0;
-  for (int pass = 0; pass < 8; ++pass) {
-    const int shift = 56 - 8 * pass;
+  if (kmin == kmax) return kmin;
+  const int top = 63 - __builtin_clzll(kmin ^ kmax);      // highest differing bit
+  int shift = (top / 8) * 8;
+  // the bytes above `shift + 8` are the same in every key
+  uint64_t prefix = (shift + 8 >= 64) ? 0ull : ((kmin >> (shift + 8)) << (shift + 8));
+  for (; shift >= 0; shift -= 8) {
     for (int i = tid; i < 256; i += WG) s.hist[i] = 0u;
     __syncthreads();
-    const uint64_t hmask = pass == 0 ? 0ull : (~0ull << (shift + 8));
+    const uint64_t hmask = (shift + 8 >= 64) ? 0ull : (~0ull << (shift + 8));
     for (int i = tid; i < n; i += WG) {
-      const uint64_t k = integ_key<INT>(s.val[i]);
+      const uint64_t k = integ_key<INT>(vals[i]);
       if ((k & hmask) == prefix) atomicAdd(&s.hist[(k >> shift) & 255u], 1u);
     }
     __syncthreads();
@@ -307,24 +313,61 @@ __device__ uint64_t integ_select(const IntegSm& s, int n, uint32_t r) {
   return prefix;
 }
 
+// the two middle order statistics' keys (equal for odd n): the lower by radix
+// select, the upper as the same key when it occurs often enough, else the
+// smallest key above it
+template <bool INT>
+__device__ void integ_middle(const IntegSm& s, const uint64_t* vals, int n, uint64_t& k0, uint64_t& k1) {
+  const int tid = thread_id();
+  uint64_t mn = ~0ull, mx = 0ull;
+  for (int i = tid; i < n; i += WG) {
+    const uint64_t k = integ_key<INT>(vals[i]);
+    mn = k < mn ? k : mn;
+    mx = k > mx ? k : mx;
+  }
+  const uint64_t kmin = (uint64_t)block_reduce_i64((int64_t)(mn ^ 0x8000000000000000ull), s.red,
+                                                   [](int64_t a, int64_t b) { return a < b ? a : b; }) ^
+                        0x8000000000000000ull;
+  const uint64_t kmax = (uint64_t)block_reduce_i64((int64_t)(mx ^ 0x8000000000000000ull), s.red,
+                                                   [](int64_t a, int64_t b) { return a > b ? a : b; }) ^
+                        0x8000000000000000ull;
+  const uint32_t r0 = (uint32_t)((n - 1) / 2), r1 = (uint32_t)(n / 2);
+  k0 = integ_select<INT>(s, vals, n, r0, kmin, kmax);
+  if (r1 == r0) {
+    k1 = k0;
+    return;
+  }
+  int le = 0;
+  uint64_t above = ~0ull;
+  for (int i = tid; i < n; i += WG) {
+    const uint64_t k = integ_key<INT>(vals[i]);
+    le += k <= k0 ? 1 : 0;
+    if (k > k0 && k < above) above = k;
+  }
+  const int64_t cnt = block_reduce_i64((int64_t)le, s.red, [](int64_t a, int64_t b) { return a + b; });
+  const uint64_t nxt = (uint64_t)block_reduce_i64((int64_t)(above ^ 0x8000000000000000ull), s.red,
+                                                  [](int64_t a, int64_t b) { return a < b ? a : b; }) ^
+                       0x8000000000000000ull;
+  k1 = cnt > (int64_t)r1 ? k0 : nxt;
+}
+
 // ---------------------------------------------------------------- 1-D SumThreshold + SIR
-// Flags the n values in s.val (mask words in s.mask, which start cleared):
+// Flags the n values in vals (mask words in s.mask, which start cleared):
 // median, stddev and thresholds of the series, nl SumThreshold levels with
 // windows of I = 2^k <= n (level-synchronous, flagged samples out of sum and
 // count), then the SIR step.  Thread t takes the positions [t*SEG, t*SEG + SEG).
 template <bool INT>
-__device__ void integ_flag_series(const IntegSm& s, int n, int nl, const DevParams& P, double* med_out,
-                                  double* sd_out) {
+__device__ void integ_flag_series(const IntegSm& s, const uint64_t* vals, int n, int nl, const DevParams& P,
+                                  double* med_out, double* sd_out) {
   const int tid = thread_id();
   const int nw = (n + 63) >> 6;
   for (int i = tid; i < nw; i += WG) s.mask[i] = 0ull;
   // median (numpy definition) and stddev
-  const uint32_t r0 = (uint32_t)((n - 1) / 2), r1 = (uint32_t)(n / 2);
-  const uint64_t k0 = integ_select<INT>(s, n, r0);
-  const uint64_t k1 = (r1 == r0) ? k0 : integ_select<INT>(s, n, r1);
+  uint64_t k0, k1;
+  integ_middle<INT>(s, vals, n, k0, k1);
   const double v0 = integ_key_value<INT>(k0), v1 = integ_key_value<INT>(k1);
   const double med = (n & 1) ? v0 : (v0 + v1) / 2.0;
-  const double sd = integ_stddev<INT>(s, n);
+  const double sd = integ_stddev<INT>(s, vals, n);
   if (tid == 0) {
     double pk = 1.0;
     for (int k = 0; k < 16; ++k) {
@@ -366,8 +409,8 @@ __device__ void integ_flag_series(const IntegSm& s, int n, int nl, const DevPara
         const bool fl = (s.mask[j >> 6] >> (j & 63)) & 1ull;
         if (!fl) {
           ++cnt;
-          if (INT) Si += (int64_t)s.val[j];
-          else Sf += __longlong_as_double((long long)s.val[j]);
+          if (INT) Si += (int64_t)vals[j];
+          else Sf += __longlong_as_double((long long)vals[j]);
         }
       }
       for (int st = a; st < s_end; ++st) {
@@ -375,13 +418,13 @@ __device__ void integ_flag_series(const IntegSm& s, int n, int nl, const DevPara
           const int out = st - 1, in = st + I - 1;
           if (!((s.mask[out >> 6] >> (out & 63)) & 1ull)) {
             --cnt;
-            if (INT) Si -= (int64_t)s.val[out];
-            else Sf -= __longlong_as_double((long long)s.val[out]);
+            if (INT) Si -= (int64_t)vals[out];
+            else Sf -= __longlong_as_double((long long)vals[out]);
           }
           if (!((s.mask[in >> 6] >> (in & 63)) & 1ull)) {
             ++cnt;
-            if (INT) Si += (int64_t)s.val[in];
-            else Sf += __longlong_as_double((long long)s.val[in]);
+            if (INT) Si += (int64_t)vals[in];
+            else Sf += __longlong_as_double((long long)vals[in]);
           }
         }
         bool h;
@@ -416,7 +459,7 @@ __device__ void integ_flag_series(const IntegSm& s, int n, int nl, const DevPara
       if (tid == 0) {
         const FastDiv fd((uint32_t)P.eta_den);
         ProseScan f{0u, 0};
-        uint64_t* out = s.val;   // the values are no longer needed: reuse as output words
+        uint64_t* out = s.part;   // forward result words (n / 64 <= 256 <= NW * 64)
         for (int w = 0; w < nw; ++w) {
           const int nb = min(64, n - 64 * w);
           out[w] = prose_fwd_word(s.mask[w] & lowmask(nb), 64 * w, nb, f, (uint32_t)P.eta_num, fd);
@@ -470,49 +513,78 @@ __device__ void phase_integrated(const DevBlock& b, const DevParams& P, const In
   for (int i = tid; i < C; i += WG) s.spec[i] = 0ull;
   for (int i = tid; i < 17; i += WG) s.cmask[i] = 0ull;
   __syncthreads();
-  // one pass: column sums in registers (each thread owns its columns), row sums
-  // by a wave reduction per row (exact integer atomics, or per-wave partials
-  // added in wave order for float input)
-  uint64_t ci[4][8];
+  // one pass: column sums in registers (each thread owns its columns; integer
+  // column sums stay below 2^25), row sums by wave reductions, RB rows at a time
+  // so that their loads are in flight together (exact integer atomics, or
+  // per-wave partials added in wave order for float input)
+  constexpr int RB = 4;
+  uint32_t ci[4][8];
   double cf[4][8];
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      ci[q][j] = 0ull;
+      ci[q][j] = 0u;
       cf[q][j] = 0.0;
     }
   for (int r0 = 0; r0 < C; r0 += 64) {
     const int r1 = min(C, r0 + 64);
-    for (int row = r0; row < r1; ++row) {
-      uint64_t rs_i = 0;
-      double rs_f = 0.0;
+    for (int rb = r0; rb < r1; rb += RB) {
+      uint32_t rsi[RB];
+      double rsf[RB];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        rsi[u] = 0u;
+        rsf[u] = 0.0;
+      }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int t0 = (tid + q * WG) * 8;
         if (q < nq && t0 < T) {
-          VT v[8];
-          integ_load8<INT>(b, row, t0, v);
+          VT v[RB][8];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            if (INT) {
-              ci[q][j] += (uint64_t)v[j];
-              rs_i += (uint64_t)v[j];
+          for (int u = 0; u < RB; ++u) {
+            if (rb + u < r1) {
+              integ_load8<INT>(b, rb + u, t0, v[u]);
             } else {
-              cf[q][j] += (double)v[j];
-              rs_f += (double)v[j];
+#pragma unroll
+              for (int j = 0; j < 8; ++j) v[u][j] = (VT)0;
             }
           }
+#pragma unroll
+          for (int u = 0; u < RB; ++u)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              if (INT) {
+                ci[q][j] += (uint32_t)v[u][j];
+                rsi[u] += (uint32_t)v[u][j];
+              } else {
+                cf[q][j] += (double)v[u][j];
+                rsf[u] += (double)v[u][j];
+              }
+            }
         }
+        // one chunk's RB loads in flight at a time: hoisting all chunks' loads
+        // would hold 4 x RB x 8 values
+        __builtin_amdgcn_sched_barrier(0);
       }
-      if (INT) {
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) rs_i += (uint64_t)__shfl_xor((long long)rs_i, d);
-        if (lane == 0 && rs_i) atomicAdd((unsigned long long*)&s.spec[row], (unsigned long long)rs_i);
-      } else {
+      for (int d = 32; d >= 1; d >>= 1)
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) rs_f += __shfl_xor(rs_f, d);
-        if (lane == 0) s.part[wv * 64 + (row - r0)] = (uint64_t)__double_as_longlong(rs_f);
+        for (int u = 0; u < RB; ++u) {
+          if (INT) rsi[u] += __shfl_xor(rsi[u], d);
+          else rsf[u] += __shfl_xor(rsf[u], d);
+        }
+      if (lane == 0) {
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+          if (rb + u >= r1) continue;
+          if (INT) {
+            if (rsi[u]) atomicAdd((unsigned long long*)&s.spec[rb + u], (unsigned long long)rsi[u]);
+          } else {
+            s.part[wv * 64 + (rb + u - r0)] = (uint64_t)__double_as_longlong(rsf[u]);
+          }
+        }
       }
     }
     if (!INT) {
@@ -525,12 +597,20 @@ __device__ void phase_integrated(const DevBlock& b, const DevParams& P, const In
       __syncthreads();
     }
   }
+  // the all-channel time series into LDS (each thread writes only its columns)
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int t0 = (tid + q * WG) * 8;
+    if (q < nq && t0 < T) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (t0 + j < T) s.val[t0 + j] = INT ? (uint64_t)ci[q][j] : (uint64_t)__double_as_longlong(cf[q][j]);
+    }
+  }
   __syncthreads();
   // spectrum: flag along frequency first
-  for (int i = tid; i < C; i += WG) s.val[i] = s.spec[i];
-  __syncthreads();
   double med, sd;
-  integ_flag_series<INT>(s, C, min(P.nl_f, ST_MAX_LEVELS), P, &med, &sd);
+  integ_flag_series<INT>(s, s.spec, C, min(P.nl_f, ST_MAX_LEVELS), P, &med, &sd);
   for (int i = tid; i < (C + 63) / 64; i += WG) s.cmask[i] = s.mask[i];
   if (INT) {
     // the rows' exact power sums, for the history flagger
@@ -547,49 +627,40 @@ __device__ void phase_integrated(const DevBlock& b, const DevParams& P, const In
       while (m) {
         const int row = 64 * w + __builtin_ctzll(m);
         m &= m - 1;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < nq; ++q) {
           const int t0 = (tid + q * WG) * 8;
-          if (q < nq && t0 < T) {
+          if (t0 < T) {
             VT v[8];
             integ_load8<INT>(b, row, t0, v);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) ci[q][j] -= (uint64_t)v[j];
+            for (int j = 0; j < 8; ++j)
+              if (t0 + j < T) s.val[t0 + j] -= (uint64_t)v[j];
           }
         }
       }
     }
   } else if (nflag > 0) {
     // float input: the sums over the unflagged channels again, in row order
+    for (int q = 0; q < nq; ++q) {
+      const int t0 = (tid + q * WG) * 8;
+      if (t0 >= T) continue;
+      double acc[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+      for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+      for (int row = 0; row < C; ++row) {
+        if ((s.cmask[row >> 6] >> (row & 63)) & 1ull) continue;
+        VT v[8];
+        integ_load8<INT>(b, row, t0, v);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) cf[q][j] = 0.0;
-    for (int row = 0; row < C; ++row) {
-      if ((s.cmask[row >> 6] >> (row & 63)) & 1ull) continue;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int t0 = (tid + q * WG) * 8;
-        if (q < nq && t0 < T) {
-          VT v[8];
-          integ_load8<INT>(b, row, t0, v);
-#pragma unroll
-          for (int j = 0; j < 8; ++j) cf[q][j] += (double)v[j];
-        }
+        for (int j = 0; j < 8; ++j) acc[j] += (double)v[j];
       }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int t0 = (tid + q * WG) * 8;
-    if (q < nq && t0 < T) {
 #pragma unroll
       for (int j = 0; j < 8; ++j)
-        if (t0 + j < T) s.val[t0 + j] = INT ? ci[q][j] : (uint64_t)__double_as_longlong(cf[q][j]);
+        if (t0 + j < T) s.val[t0 + j] = (uint64_t)__double_as_longlong(acc[j]);
     }
   }
   __syncthreads();
-  integ_flag_series<INT>(s, T, min(P.nl_t, ST_MAX_LEVELS), P, &med, &sd);
+  integ_flag_series<INT>(s, s.val, T, min(P.nl_t, ST_MAX_LEVELS), P, &med, &sd);
   // the block's mask words: a flagged channel's whole row, else the time flags
   GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
   for (int i = tid; i < C * W; i += WG) {

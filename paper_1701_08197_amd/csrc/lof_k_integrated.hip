@@ -6,7 +6,7 @@
 namespace lofk {
 
 template <bool INT>
-__global__ __launch_bounds__(WG) void lof_integrated_kernel(const DevBlock* __restrict__ blocks, int nb, int maxch,
+__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_integrated_kernel(const DevBlock* __restrict__ blocks, int nb, int maxch,
                                                            int* counter, DevParams P) {
   // 16-byte aligned: the areas carved from it hold 8-byte values and 64-bit LDS
   // atomics, and the array follows the work loop's 4-byte static variable

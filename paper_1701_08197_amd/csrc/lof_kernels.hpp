@@ -1320,9 +1320,13 @@ __device__ __forceinline__ uint64_t sir_runs_lane(uint64_t bits, int n, int a, i
   int K = 0, alpha = alpha0, pos = 0;
   // no gaps, or nothing flagged anywhere near: nothing to add
   bool more = z != 0 && (bits != 0 || alpha0 > 0 || beta0 > 0);
+  int kw = SIR_RUNS;   // stretches seen by the wave (uniform): the backward pass skips the rest
 #pragma unroll
   for (int k = 0; k < SIR_RUNS; ++k) {
-    if (__ballot(more) == 0) break;
+    if (__ballot(more) == 0) {
+      kw = k;
+      break;
+    }
     if (more) {
       const uint64_t rest = z >> pos;
       if (rest == 0) {
@@ -1345,7 +1349,7 @@ __device__ __forceinline__ uint64_t sir_runs_lane(uint64_t bits, int n, int a, i
   int beta = beta0, nxt = n;
 #pragma unroll
   for (int k = SIR_RUNS - 1; k >= 0; --k) {
-    if (__ballot(k < K) == 0) continue;
+    if (k >= kw) continue;
     if (k < K) {
       const int s0 = (int)(st[k] & 63u), len = (int)((st[k] >> 6) & 127u), al = (int)(st[k] >> 13);
       const int e = s0 + len;
