@@ -19,6 +19,7 @@ the input is integer), favouring obviousness over speed:
                                                  van de Gronde et al. 2016)
 * history flagger ............................. Sec. 4.1 (pseudocode and Fig. "history")
 * integrated pre-correlation mode ............. Sec. 4 (integration paragraph, Fig. "integrate")
+* robust stddev from the MAD .................. Sec. 4.2 (statistics list)
 
 Where the paper is silent or garbled, each function states the reading it
 implements.  Window sums are brute force
@@ -58,6 +59,7 @@ class Params:
     history_min: int = 4
     literal_history_tie: bool = False  # True: flag when cur >= thr (listing's else-branch)
     sir_prose: bool = False            # True: the prose reading of Sec. 2.2 (sir_prose_rows)
+    robust_sigma: bool = False         # True: stddev from the MAD (block_mad_sigma, Sec. 4.2)
 
     @property
     def levels_freq(self) -> int:
@@ -126,6 +128,24 @@ def block_stddev(p: np.ndarray, exact: bool) -> float:
     if var < 0.0:
         var = 0.0
     return math.sqrt(var)
+
+
+MAD_TO_SIGMA = 1.4826   # stddev of a normal distribution per unit of its MAD (1 / 0.6745)
+
+
+def block_mad_sigma(p: np.ndarray, exact: bool) -> float:
+    """Robust stddev of the block (Sec. 4.2 lists the MAD among the statistics
+    used): 1.4826 * median(|p - median(p)|), both medians with the numpy
+    definition.  Integer input: |2p - 2 median| are integers, so the MAD is exact
+    (an integer or a half-integer, then halved); the product is one float64
+    rounding."""
+    med = block_median(p)
+    if exact:
+        d2 = np.abs(2 * p.astype(np.int64).ravel() - int(round(2 * med)))
+        mad = block_median(d2) / 2.0
+    else:
+        mad = block_median(np.abs(p.ravel() - med))
+    return MAD_TO_SIGMA * mad
 
 
 def level_factors(params: Params, n: int) -> list[float]:
@@ -337,7 +357,7 @@ def flag_block(x: np.ndarray, dtype: int, params: Params = Params(),
     p = power(x, dtype)
     C, T = p.shape
     med = block_median(p)
-    sd = block_stddev(p, exact)
+    sd = block_mad_sigma(p, exact) if params.robust_sigma else block_stddev(p, exact)
     th = thresholds(med, sd, params)
     st = sumthreshold_block(p, th, params, exact)
     sm = sir_block(st, params)
@@ -384,7 +404,7 @@ def series_stddev(v: np.ndarray, exact: bool) -> float:
 def series_thresholds(v: np.ndarray, params: Params, exact: bool, n_levels: int):
     """(median, stddev, thresholds) of one integrated 1-D series (Sec. 2.1)."""
     med = block_median(v)
-    sd = series_stddev(v, exact)
+    sd = block_mad_sigma(v, exact) if params.robust_sigma else series_stddev(v, exact)
     return med, sd, thresholds(med, sd, params, max(1, n_levels))
 
 

@@ -617,3 +617,56 @@ def test_series_stddev_exact_beyond_64_bits():
     mu = Fraction(sum(vals), 4)
     var = Fraction(sum(a * a for a in vals), 4) - mu * mu
     assert O.series_stddev(v, True) == pytest.approx(math.sqrt(float(var)), rel=1e-15)
+
+
+# ------------------------------------------------------------ robust stddev (MAD)
+# Sec. 4.2 lists the MAD among the statistics; 1.4826 * MAD estimates the stddev
+# of normal noise without the RFI it is meant to find.
+def test_mad_sigma_hand_worked():
+    p = np.array([[1, 2, 3, 4, 100]], dtype=np.int64)          # median 3, |p - 3| = 2 1 0 1 97
+    assert O.block_mad_sigma(p, True) == 1.4826 * 1.0
+    q = np.array([[1, 2, 4, 7]], dtype=np.int64)                # median 3, |q - 3| = 2 1 1 4 -> 1.5
+    assert O.block_mad_sigma(q, True) == 1.4826 * 1.5
+    r = np.array([[1, 2, 3, 6]], dtype=np.int64)                # median 2.5, |r - 2.5| = 1.5 .5 .5 3.5 -> 1
+    assert O.block_mad_sigma(r, True) == 1.4826 * 1.0
+    assert O.block_mad_sigma(p.astype(np.float64), False) == 1.4826 * 1.0
+
+
+def test_mad_sigma_ignores_outlier_size():
+    rng = np.random.default_rng(3)
+    p = rng.integers(0, 1000, size=(8, 125))
+    base = O.block_mad_sigma(p, True)
+    q = p.copy()
+    q[p > 900] = 10 ** 6                                       # far beyond median + MAD already
+    assert O.block_mad_sigma(q, True) == base
+    assert O.block_stddev(q, True) > 10 * O.block_stddev(p, True)
+
+
+def test_mad_sigma_estimates_normal_stddev():
+    rng = np.random.default_rng(4)
+    x = rng.normal(10.0, 2.0, size=200_000)
+    assert O.block_mad_sigma(x, False) == pytest.approx(2.0, rel=0.01)
+
+
+def test_mad_sigma_int_equals_float_on_integers():
+    rng = np.random.default_rng(6)
+    for n in (1, 2, 3, 10, 101, 1000):
+        p = rng.integers(0, 5000, size=n)
+        assert O.block_mad_sigma(p, True) == O.block_mad_sigma(p.astype(np.float64), False)
+
+
+def test_robust_sigma_finds_tones_the_classic_stddev_hides():
+    # three strong tone channels among 64 inflate the spectrum's stddev so much
+    # that 6 sigma misses them; the MAD-based stddev does not
+    rng = np.random.default_rng(9)
+    C, T = 64, 512
+    pw = rng.integers(90, 111, size=(C, T)).astype(np.int64)
+    for ch in (5, 21, 40):
+        pw[ch] = 900
+    sq = np.rint(np.sqrt(pw)).astype(np.int64)
+    x = np.zeros((C, T, 2), dtype=np.int8)
+    x[..., 0] = sq
+    prm = O.Params(sir_eta_num=0)
+    assert not O.integrated_block(x, O.CI8, prm).channel_flags.any()
+    r = O.integrated_block(x, O.CI8, O.Params(sir_eta_num=0, robust_sigma=True))
+    assert r.channel_flags.nonzero()[0].tolist() == [5, 21, 40]
