@@ -131,7 +131,16 @@ def _gen_range(args):
 def make_config1(nb: int, workers: int, start_method: str = "fork", second: int = 0):
     """All blocks of one second of the 48-station observation, generated in
     parallel; returns (array view, shared-memory handle).  Use
-    start_method="spawn" once the GPU runtime is initialised in this process."""
+    start_method="spawn" once the GPU runtime is initialised in this process.
+    workers <= 1 generates in this process, with no child process or shared
+    memory (profilers that follow children can stall on pool teardown)."""
+    if workers <= 1:
+        arr = np.empty((nb, C, T, 2), dtype=np.int8)
+        for b in range(nb):
+            arr[b] = synth.config1_block(b, second)
+            if b % 1024 == 1023:
+                progress(f"second {second}: {b + 1} of {nb} blocks generated")
+        return arr, None
     from multiprocessing import shared_memory
     shm = shared_memory.SharedMemory(create=True, size=nb * C * T * 2)
     chunks = []
@@ -146,6 +155,10 @@ def make_config1(nb: int, workers: int, start_method: str = "fork", second: int 
     return arr, shm
 
 
+def progress(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def resident_seconds(nb: int, n_seconds: int, workers: int, dev):
     """n_seconds of config-1 data as device tensors [nb, C, T, 2]."""
     import torch
@@ -154,8 +167,10 @@ def resident_seconds(nb: int, n_seconds: int, workers: int, dev):
         host, shm = make_config1(nb, workers, "spawn" if torch.cuda.is_initialized() else "fork", second=s)
         out.append(torch.from_numpy(host).to(dev))
         del host
-        shm.close()
-        shm.unlink()
+        if shm is not None:
+            shm.close()
+            shm.unlink()
+        progress(f"second {s} generated and resident")
     return out
 
 
@@ -260,6 +275,7 @@ def run_second(args, cores, integrated=False):
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
+    progress(f"{args.warmup} warm-up steps done")
     K = args.steps
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     torch.cuda.synchronize()
@@ -268,6 +284,7 @@ def run_second(args, cores, integrated=False):
         step(args.warmup + k, *evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    progress(f"{K} timed steps done")
     call_ms = [a.elapsed_time(b) for a, b in evs]
     ms_per_step = wall * 1e3 / K
     samples = nb * C * T
@@ -290,6 +307,7 @@ def run_second(args, cores, integrated=False):
         fp.flag_blocks_raw(tables[k % len(tables)], nb, sh)
     tot, n = fp.phase_times()
     fp.close()
+    progress("per-phase timing run done")
     phase_ms = {k: v / max(1, n) for k, v in tot.items()}
     dom = max(phase_ms, key=phase_ms.get)
     dom_bytes = samples * (INTEGRATED_BYTES_PER_SAMPLE[dom] if integrated else PHASE_BYTES_PER_SAMPLE[dom])

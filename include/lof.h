@@ -92,6 +92,12 @@ typedef enum {
                                             entry holds the time series' median, stddev
                                             and thresholds.  Complex int8 input stays
                                             exact (64-bit sums, 128-bit moments).      */
+#define LOF_OPT_ROBUST_SIGMA 0x40u       /* robust statistics (Sec. 4.2 lists the MAD):
+                                            stddev := 1.4826 * median(|x - median(x)|)
+                                            in the thresholds, for full-rate blocks and
+                                            for the integrated mode's series; complex int8
+                                            input stays exact (the deviations are
+                                            integers or half-integers)                 */
 
 /* Phases of the path, in launch order (lof_phase_times) */
 #define LOF_PHASE_STATS 0        /* power, median, stddev, thresholds (Sec. 2.1, 4.2)   */

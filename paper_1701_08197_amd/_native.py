@@ -21,6 +21,7 @@ LOF_OPT_GRAPH = 0x4
 LOF_OPT_PHASE_TIMING = 0x8
 LOF_OPT_SIR_PROSE = 0x10
 LOF_OPT_INTEGRATED = 0x20
+LOF_OPT_ROBUST_SIGMA = 0x40
 # phases of lof_phase_times, in launch order
 PHASES = ("stats", "sumthreshold_time", "sumthreshold_freq", "sir_time", "sir_freq", "history_write")
 LOF_N_PHASES = len(PHASES)

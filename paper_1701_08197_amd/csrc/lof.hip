@@ -204,7 +204,7 @@ DevParams dev_params(const lof_ctx* c, uint64_t* mask, uint64_t* mask2, BlockSta
   P.prose = (c->prm.options & LOF_OPT_SIR_PROSE) ? 1 : 0;
   P.integrated = (c->prm.options & LOF_OPT_INTEGRATED) ? 1 : 0;
   P.integ_tmax = 0;
-  P._pad = 0;
+  P.robust = (c->prm.options & LOF_OPT_ROBUST_SIGMA) ? 1 : 0;
   P.ring = c->ring;
   P.rcount = c->rcount;
   P.rhead = c->rhead;

@@ -131,7 +131,7 @@ struct DevParams {
   int32_t prose;         // the range-extension reading of the SIR step
   int32_t integrated;    // integrated pre-correlation mode
   int32_t integ_tmax;    // longest block of the call (integrated mode: LDS layout)
-  int32_t _pad;
+  int32_t robust;        // stddev from the MAD
   double* ring;          // [streams][maxC][H]
   int32_t* rcount;       // [streams][maxC]
   int32_t* rhead;        // [streams][maxC]

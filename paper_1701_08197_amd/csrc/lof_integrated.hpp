@@ -75,6 +75,26 @@ __device__ __forceinline__ int64_t block_reduce_i64(int64_t x, int64_t* red, F&&
   return r;
 }
 
+// sums of four 64-bit integers over the workgroup at once (one set of barriers)
+__device__ __forceinline__ void block_sum4_i64(int64_t (&x)[4], int64_t* red) {
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] += (int64_t)__shfl_xor((long long)x[k], d);
+  __syncthreads();
+  const int64_t mine = lane == 0 ? x[0] : (lane == 1 ? x[1] : (lane == 2 ? x[2] : x[3]));
+  if (lane < 4) red[4 * wv + lane] = mine;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int64_t r = 0;
+    for (int w = 0; w < NW; ++w) r += red[4 * w + k];
+    x[k] = r;
+  }
+  __syncthreads();
+}
+
 // sum of doubles in a fixed order: lanes by a shuffle tree, waves in order
 __device__ __forceinline__ double block_sum_f64(double x, int64_t* red) {
   const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
@@ -150,7 +170,7 @@ __device__ __forceinline__ int block_scan_max_excl_rev(int x, int64_t* red) {
 // quotient's top 53 bits, the next bit and whether anything nonzero follows
 // (lower quotient bits or a remainder) give the rounding; the result is scaled
 // back by 2^-k.
-__device__ inline double u128_div_rn(uint64_t hi, uint64_t lo, uint64_t n) {
+__device__ __forceinline__ double u128_div_rn(uint64_t hi, uint64_t lo, uint64_t n) {
   if (hi == 0 && lo == 0) return 0.0;
   const int bl_s = hi ? 128 - __builtin_clzll(hi) : 64 - __builtin_clzll(lo);
   const int bl_n = 64 - __builtin_clzll(n);
@@ -202,7 +222,7 @@ __device__ inline double u128_div_rn(uint64_t hi, uint64_t lo, uint64_t n) {
 
 // population stddev of the n series values in vals, with the oracle's formula
 template <bool INT>
-__device__ double integ_stddev(const IntegSm& s, const uint64_t* vals, int n) {
+__device__ __forceinline__ double integ_stddev(const IntegSm& s, const uint64_t* vals, int n) {
   const int tid = thread_id();
   if constexpr (INT) {
     unsigned __int128 s2 = 0;
@@ -212,15 +232,12 @@ __device__ double integ_stddev(const IntegSm& s, const uint64_t* vals, int n) {
       s1 += v;
       s2 += (unsigned __int128)v * v;
     }
-    const int64_t S1 = block_reduce_i64((int64_t)s1, s.red, [](int64_t a, int64_t b) { return a + b; });
-    // 128-bit sum: low and high words separately, the carries from the low words
-    // counted exactly (each thread's low word is < 2^64; sums of 512 of them need
-    // 73 bits, kept as a carry count)
+    // 128-bit sum: the low word in two 32-bit halves (sums of 512 of them stay
+    // below 2^41) and the high word, all added exactly
     const uint64_t lo = (uint64_t)s2, hi = (uint64_t)(s2 >> 64);
-    const uint64_t lo_lo = lo & 0xffffffffull, lo_hi = lo >> 32;
-    const int64_t A = block_reduce_i64((int64_t)lo_lo, s.red, [](int64_t a, int64_t b) { return a + b; });
-    const int64_t B = block_reduce_i64((int64_t)lo_hi, s.red, [](int64_t a, int64_t b) { return a + b; });
-    const int64_t Hs = block_reduce_i64((int64_t)hi, s.red, [](int64_t a, int64_t b) { return a + b; });
+    int64_t v4[4] = {(int64_t)s1, (int64_t)(lo & 0xffffffffull), (int64_t)(lo >> 32), (int64_t)hi};
+    block_sum4_i64(v4, s.red);
+    const int64_t S1 = v4[0], A = v4[1], B = v4[2], Hs = v4[3];
     // S2 = Hs * 2^64 + B * 2^32 + A (A, B < 2^41)
     const unsigned __int128 S2 = ((unsigned __int128)(uint64_t)Hs << 64) + ((unsigned __int128)(uint64_t)B << 32) +
                                  (unsigned __int128)(uint64_t)A;
@@ -261,9 +278,9 @@ __device__ __forceinline__ double integ_key_value(uint64_t k) {
 // the key of rank r (0-based) among the n values, by 8-bit digits from the most
 // significant byte in which the smallest and largest key differ (every key
 // shares the bytes above it); kmin / kmax are the extreme keys
-template <bool INT>
-__device__ uint64_t integ_select(const IntegSm& s, const uint64_t* vals, int n, uint32_t r, uint64_t kmin,
-                                 uint64_t kmax) {
+template <class KF>
+__device__ __forceinline__ uint64_t integ_select(const IntegSm& s, const uint64_t* vals, int n, uint32_t r,
+                                                 uint64_t kmin, uint64_t kmax, KF key) {
   const int tid = thread_id(), lane = tid & 63;
   if (kmin == kmax) return kmin;
   const int top = 63 - __builtin_clzll(kmin ^ kmax);      // highest differing bit
@@ -275,7 +292,7 @@ __device__ uint64_t integ_select(const IntegSm& s, const uint64_t* vals, int n, 
     __syncthreads();
     const uint64_t hmask = (shift + 8 >= 64) ? 0ull : (~0ull << (shift + 8));
     for (int i = tid; i < n; i += WG) {
-      const uint64_t k = integ_key<INT>(vals[i]);
+      const uint64_t k = key(vals[i]);
       if ((k & hmask) == prefix) atomicAdd(&s.hist[(k >> shift) & 255u], 1u);
     }
     __syncthreads();
@@ -316,12 +333,13 @@ __device__ uint64_t integ_select(const IntegSm& s, const uint64_t* vals, int n, 
 // the two middle order statistics' keys (equal for odd n): the lower by radix
 // select, the upper as the same key when it occurs often enough, else the
 // smallest key above it
-template <bool INT>
-__device__ void integ_middle(const IntegSm& s, const uint64_t* vals, int n, uint64_t& k0, uint64_t& k1) {
+template <class KF>
+__device__ __forceinline__ void integ_middle(const IntegSm& s, const uint64_t* vals, int n, KF key, uint64_t& k0,
+                                             uint64_t& k1) {
   const int tid = thread_id();
   uint64_t mn = ~0ull, mx = 0ull;
   for (int i = tid; i < n; i += WG) {
-    const uint64_t k = integ_key<INT>(vals[i]);
+    const uint64_t k = key(vals[i]);
     mn = k < mn ? k : mn;
     mx = k > mx ? k : mx;
   }
@@ -332,7 +350,7 @@ __device__ void integ_middle(const IntegSm& s, const uint64_t* vals, int n, uint
                                                    [](int64_t a, int64_t b) { return a > b ? a : b; }) ^
                         0x8000000000000000ull;
   const uint32_t r0 = (uint32_t)((n - 1) / 2), r1 = (uint32_t)(n / 2);
-  k0 = integ_select<INT>(s, vals, n, r0, kmin, kmax);
+  k0 = integ_select(s, vals, n, r0, kmin, kmax, key);
   if (r1 == r0) {
     k1 = k0;
     return;
@@ -340,7 +358,7 @@ __device__ void integ_middle(const IntegSm& s, const uint64_t* vals, int n, uint
   int le = 0;
   uint64_t above = ~0ull;
   for (int i = tid; i < n; i += WG) {
-    const uint64_t k = integ_key<INT>(vals[i]);
+    const uint64_t k = key(vals[i]);
     le += k <= k0 ? 1 : 0;
     if (k > k0 && k < above) above = k;
   }
@@ -357,17 +375,36 @@ __device__ void integ_middle(const IntegSm& s, const uint64_t* vals, int n, uint
 // windows of I = 2^k <= n (level-synchronous, flagged samples out of sum and
 // count), then the SIR step.  Thread t takes the positions [t*SEG, t*SEG + SEG).
 template <bool INT>
-__device__ void integ_flag_series(const IntegSm& s, const uint64_t* vals, int n, int nl, const DevParams& P,
+__device__ __forceinline__ void integ_flag_series(const IntegSm& s, const uint64_t* vals, int n, int nl, const DevParams& P,
                                   double* med_out, double* sd_out) {
   const int tid = thread_id();
   const int nw = (n + 63) >> 6;
   for (int i = tid; i < nw; i += WG) s.mask[i] = 0ull;
   // median (numpy definition) and stddev
   uint64_t k0, k1;
-  integ_middle<INT>(s, vals, n, k0, k1);
+  integ_middle(s, vals, n, [](uint64_t v) { return integ_key<INT>(v); }, k0, k1);
   const double v0 = integ_key_value<INT>(k0), v1 = integ_key_value<INT>(k1);
   const double med = (n & 1) ? v0 : (v0 + v1) / 2.0;
-  const double sd = integ_stddev<INT>(s, vals, n);
+  double sd;
+  if (P.robust) {
+    // 1.4826 * MAD: the middle order statistics of the deviations from the
+    // median (integer series: doubled deviations |2v - med2|, exact)
+    uint64_t m0, m1;
+    double mad;
+    if (INT) {
+      const uint64_t med2 = k0 + k1;
+      integ_middle(s, vals, n, [med2](uint64_t v) { return 2 * v > med2 ? 2 * v - med2 : med2 - 2 * v; }, m0, m1);
+      mad = ((double)m0 + (double)m1) / 4.0;
+    } else {
+      integ_middle(s, vals, n, [med](uint64_t v) {
+        return integ_key<false>((uint64_t)__double_as_longlong(__builtin_fabs(__longlong_as_double((long long)v) - med)));
+      }, m0, m1);
+      mad = (integ_key_value<false>(m0) + integ_key_value<false>(m1)) / 2.0;
+    }
+    sd = MAD_TO_SIGMA * mad;
+  } else {
+    sd = integ_stddev<INT>(s, vals, n);
+  }
   if (tid == 0) {
     double pk = 1.0;
     for (int k = 0; k < 16; ++k) {
@@ -383,7 +420,9 @@ __device__ void integ_flag_series(const IntegSm& s, const uint64_t* vals, int n,
   *med_out = med;
   *sd_out = sd;
   __syncthreads();
-  const int a = tid * INTEG_SEG;
+  // thread t takes the positions [t*seg, t*seg + seg), seg <= 32
+  const int seg = (n + WG - 1) / WG;
+  const int a = tid * seg;
   for (int k = 0; k < nl && k < ST_MAX_LEVELS; ++k) {
     const int I = 1 << k;
     if (I > n) break;
@@ -400,7 +439,7 @@ __device__ void integ_flag_series(const IntegSm& s, const uint64_t* vals, int n,
     }
     // windows starting in this thread's positions: running sum and count
     uint32_t hits = 0;
-    const int s_end = min(a + INTEG_SEG, n - I + 1);
+    const int s_end = min(a + seg, n - I + 1);
     if (a < s_end) {
       int64_t Si = 0;
       double Sf = 0.0;
@@ -473,10 +512,17 @@ __device__ void integ_flag_series(const IntegSm& s, const uint64_t* vals, int n,
       }
       __syncthreads();
     } else {
-      // linear form, INTEG_SEG positions per thread, block scans between threads
+      // linear form, the thread's seg positions in a lane summary (up to 32),
+      // block scans between threads
       const int num = P.eta_num, den = P.eta_den;
-      const int nval = clampi(n - a, 0, INTEG_SEG);
-      const uint64_t bits = nval > 0 ? ((s.mask[a >> 6] >> (a & 63)) & lowmask(nval)) : 0ull;
+      const int nval = clampi(n - a, 0, seg);
+      uint64_t bits = 0;
+      if (nval > 0) {
+        const int w0 = a >> 6, o = a & 63;
+        bits = s.mask[w0] >> o;
+        if (o + nval > 64) bits |= s.mask[w0 + 1] << (64 - o);
+        bits &= lowmask(nval);
+      }
       const SirSum ss = sir_lane_summary<INTEG_SEG>(bits, nval, num, den);
       // exclusive prefix sum of the totals, prefix min of base + mn, suffix max of base + mx
       const int64_t tot_incl = block_scan_incl(ss.tot, s.red);
@@ -486,10 +532,14 @@ __device__ void integ_flag_series(const IntegSm& s, const uint64_t* vals, int n,
       const uint64_t out = sir_lane_apply<INTEG_SEG>(bits, nval, num, den, base, pm, sx);
       __syncthreads();
       if (nval > 0) {
+        // the segment's bits may straddle two mask words
         uint32_t* h32 = reinterpret_cast<uint32_t*>(s.mask);
-        const uint64_t sh = out << (a & 63);   // INTEG_SEG = 32: inside one word
-        if ((uint32_t)sh) atomicOr(&h32[2 * (a >> 6)], (uint32_t)sh);
-        if ((uint32_t)(sh >> 32)) atomicOr(&h32[2 * (a >> 6) + 1], (uint32_t)(sh >> 32));
+        const int w0 = a >> 6, o = a & 63;
+        const uint64_t lo = out << o, hi = o ? (out >> (64 - o)) : 0ull;
+        if ((uint32_t)lo) atomicOr(&h32[2 * w0], (uint32_t)lo);
+        if ((uint32_t)(lo >> 32)) atomicOr(&h32[2 * w0 + 1], (uint32_t)(lo >> 32));
+        if ((uint32_t)hi) atomicOr(&h32[2 * w0 + 2], (uint32_t)hi);
+        if ((uint32_t)(hi >> 32)) atomicOr(&h32[2 * w0 + 3], (uint32_t)(hi >> 32));
       }
       __syncthreads();
     }
@@ -505,7 +555,7 @@ __device__ __forceinline__ void integ_load8(const DevBlock& b, int row, int t0, 
 }
 
 template <bool INT>
-__device__ void phase_integrated(const DevBlock& b, const DevParams& P, const IntegSm& s) {
+__device__ __forceinline__ void phase_integrated(const DevBlock& b, const DevParams& P, const IntegSm& s) {
   typedef typename PowT<INT>::T VT;
   const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
   const int C = b.C, T = b.T, W = (T + 63) >> 6;

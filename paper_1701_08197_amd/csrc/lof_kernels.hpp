@@ -6,6 +6,8 @@
 
 namespace lofk {
 
+constexpr double MAD_TO_SIGMA = 1.4826;   // normal stddev per unit of MAD (1 / 0.6745)
+
 // Exact unsigned 32-bit division by a block-uniform divisor d >= 1 (round-up
 // multiplier method: l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1,
 // q = (hi + ((n - hi) >> 1)) >> (l - 1) with hi = mulhi(m, n); l = 0 for d = 1).
@@ -129,20 +131,19 @@ __device__ __forceinline__ float fkey_inv(uint32_t k) {
   return __uint_as_float((k & 0x80000000u) ? (k ^ 0x80000000u) : ~k);
 }
 
-// Radix select of the order statistics r0 <= r1 over the block's keys.
-// Integer keys: 16 bits as 12 + 4; float keys: 32 bits as 12 + 12 + 8.
-// If have_pass0, hist[0] already holds the first-digit histogram.
-template <bool INT, class SM>
-__device__ __forceinline__ void radix_select(const DevBlock& b, SM& sm, uint32_t r0, uint32_t r1, bool have_pass0,
-                             uint32_t& k0, uint32_t& k1) {
+// Radix select of the order statistics r0 <= r1 over the block's keys
+// key(power) of KB bits (16: 12 + 4, 32: 12 + 12 + 8).  If have_pass0, hist[0]
+// already holds the first-digit histogram.
+template <bool INT, int KB, class SM, class KF>
+__device__ __forceinline__ void radix_select_k(const DevBlock& b, SM& sm, uint32_t r0, uint32_t r1, bool have_pass0,
+                                               KF key, uint32_t& k0, uint32_t& k1) {
   typedef typename PowT<INT>::T VT;
   const int tid = thread_id();
   const int nch = (b.T + 7) >> 3;
   const uint32_t items = (uint32_t)b.C * (uint32_t)nch;
   const FastDiv fd((uint32_t)nch);
-  const int KB = INT ? 16 : 32;
-  const int npass = INT ? 2 : 3;
-  const int dbits[3] = {12, INT ? 4 : 12, 8};
+  const int npass = KB == 16 ? 2 : 3;
+  const int dbits[3] = {12, KB == 16 ? 4 : 12, 8};
   uint32_t pre0 = 0, pre1 = 0;
   int hi = KB;
   for (int pass = 0; pass < npass; ++pass) {
@@ -161,9 +162,9 @@ __device__ __forceinline__ void radix_select(const DevBlock& b, SM& sm, uint32_t
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           if (j < nv) {
-            const uint32_t key = INT ? (uint32_t)v[j] : fkey((float)v[j]);
-            const uint32_t top = pass == 0 ? 0u : (key >> hi);
-            const uint32_t dg = (key >> lo) & dmask;
+            const uint32_t kv = key(v[j]);
+            const uint32_t top = pass == 0 ? 0u : (kv >> hi);
+            const uint32_t dg = (kv >> lo) & dmask;
             if (top == pre0) atomicAdd(&sm.u.hist[0][dg], 1u);
             if (two && top == pre1) atomicAdd(&sm.u.hist[1][dg], 1u);
           }
@@ -183,6 +184,64 @@ __device__ __forceinline__ void radix_select(const DevBlock& b, SM& sm, uint32_t
   }
   k0 = pre0;
   k1 = pre1;
+}
+
+template <bool INT, class SM>
+__device__ __forceinline__ void radix_select(const DevBlock& b, SM& sm, uint32_t r0, uint32_t r1, bool have_pass0,
+                                             uint32_t& k0, uint32_t& k1) {
+  typedef typename PowT<INT>::T VT;
+  radix_select_k<INT, INT ? 16 : 32>(b, sm, r0, r1, have_pass0,
+                                     [](VT v) { return INT ? (uint32_t)v : fkey((float)v); }, k0, k1);
+}
+
+// Robust stddev (Sec. 4.2 lists the MAD): the value of rank `rank` among the
+// doubled deviations d = |2p - med2| (med2 = twice the median) of integer powers,
+// read from the packed 32769-bin histogram: deviation d counts the bins
+// (med2 + d) / 2 and (med2 - d) / 2 when d has the parity of med2.  Thread t
+// walks d in [128t, 128t + 128).
+template <class SM>
+__device__ uint32_t find_dev_rank(const uint32_t* h, uint32_t med2, uint32_t rank, SM& sm) {
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
+  auto bin = [&](int p) -> uint32_t {
+    if (p < 0 || p > 32768) return 0u;
+    const uint32_t w = h[p >> 1];
+    return (p & 1) ? (w >> 16) : (w & 0xffffu);
+  };
+  auto cnt = [&](uint32_t d) -> uint32_t {
+    if ((d ^ med2) & 1u) return 0u;
+    uint32_t c = bin((int)((med2 + d) >> 1));
+    if (d > 0 && d <= med2) c += bin((int)((med2 - d) >> 1));
+    return c;
+  };
+  const uint32_t d0 = (uint32_t)tid * 128u;
+  uint32_t s = 0;
+  for (uint32_t d = d0; d < d0 + 128u; ++d) s += cnt(d);
+  uint32_t x = s;
+#pragma unroll
+  for (int dd = 1; dd < 64; dd <<= 1) {
+    const uint32_t y = __shfl_up(x, dd);
+    if (lane >= dd) x += y;
+  }
+  if (lane == 63) sm.scan[wv] = x;
+  __syncthreads();
+  uint32_t off = 0;
+  for (int w = 0; w < wv; ++w) off += sm.scan[w];
+  const uint32_t excl = off + x - s;
+  if (rank >= excl && rank < excl + s) {
+    uint32_t c = excl;
+    for (uint32_t d = d0; d < d0 + 128u; ++d) {
+      const uint32_t k = cnt(d);
+      if (rank < c + k) {
+        sm.sel[0] = d;
+        break;
+      }
+      c += k;
+    }
+  }
+  __syncthreads();
+  const uint32_t v = sm.sel[0];
+  __syncthreads();
+  return v;
 }
 
 template <bool INT, class SM>
@@ -312,6 +371,28 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
   } else {
     radix_select<INT>(b, sm, r0, r1, !INT, k0, k1);
   }
+  // robust stddev: the middle order statistics of the deviations from the median
+  uint32_t m0 = 0, m1 = 0;
+  if (P.robust) {
+    if (INT) {
+      const uint32_t med2 = k0 + k1;   // twice the median (an integer)
+      if (hist_ok) {
+        m0 = find_dev_rank(sm.u.ihist, med2, r0, sm);
+        m1 = (r1 == r0) ? m0 : find_dev_rank(sm.u.ihist, med2, r1, sm);
+      } else {
+        radix_select_k<INT, 32>(b, sm, r0, r1, false, [med2](VT v) {
+          const int d = 2 * (int)(uint32_t)v - (int)med2;
+          return (uint32_t)(d < 0 ? -d : d);
+        }, m0, m1);
+      }
+    } else {
+      const double v0 = (double)fkey_inv(k0), v1 = (double)fkey_inv(k1);
+      const double med = (N & 1) ? v0 : (v0 + v1) / 2.0;
+      radix_select_k<INT, 32>(b, sm, r0, r1, false, [med](VT v) {
+        return fkey((float)__builtin_fabs((double)v - med));
+      }, m0, m1);
+    }
+  }
 
   if (tid == 0) {
     unsigned long long S1u = 0, S2u = 0;
@@ -342,7 +423,14 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
     }
     double var = ex2 - mu * mu;
     if (var < 0.0) var = 0.0;
-    const double sd = __builtin_sqrt(var);
+    double sd = __builtin_sqrt(var);
+    if (P.robust) {
+      // 1.4826 * MAD; integer input: m0, m1 are doubled deviations
+      double mad;
+      if (INT) mad = ((double)m0 + (double)m1) / 4.0;
+      else mad = (N & 1) ? (double)fkey_inv(m0) : ((double)fkey_inv(m0) + (double)fkey_inv(m1)) / 2.0;
+      sd = MAD_TO_SIGMA * mad;
+    }
     sm.median = med;
     sm.sigma = sd;
     const int nT = max(P.nl_t, P.nl_f);

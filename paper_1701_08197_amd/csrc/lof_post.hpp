@@ -46,7 +46,7 @@ __device__ __forceinline__ uint64_t sir_empty_word(int n, int c, int alpha, int 
 // Each word's effect on the best interval sums crossing it is composed along
 // the row (lane maps); a word with no flag, or flagged throughout, has a closed
 // form, the others are walked run by run in their lane.
-__device__ void post_sir_row(uint64_t* row, int W, int T, int a, int c, const FastDiv& fc, int lane) {
+__device__ __forceinline__ void post_sir_row(uint64_t* row, int W, int T, int a, int c, const FastDiv& fc, int lane) {
   const int n = lane < W ? min(64, T - 64 * lane) : 0;
   const uint64_t full = lowmask(n);
   const uint64_t x = lane < W ? (row[lane] & full) : 0ull;
@@ -66,7 +66,7 @@ __device__ void post_sir_row(uint64_t* row, int W, int T, int a, int c, const Fa
 // reads channel c's word, a bit transpose gives each lane its column, the column
 // is walked run by run in the lane (columns with no flag, or flagged throughout,
 // are left), and the new flags go back by a transpose
-__device__ void post_sir_cols(uint64_t* m, int C, int W, int w, int T, int a, int c, const FastDiv& fc,
+__device__ __forceinline__ void post_sir_cols(uint64_t* m, int C, int W, int w, int T, int a, int c, const FastDiv& fc,
                               int lane) {
   const uint64_t vcols = lowmask(min(64, T - 64 * w));
   const uint64_t x = lane < C ? (m[lane * W + w] & vcols) : 0ull;

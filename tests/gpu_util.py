@@ -28,7 +28,8 @@ def oracle_params(fp) -> O.Params:
                     history_sensitivity=fp.history_sensitivity, history_len=fp.history_len,
                     history_min=fp.history_min,
                     literal_history_tie=bool(fp.options & 0x2),
-                    sir_prose=bool(fp.options & 0x10))
+                    sir_prose=bool(fp.options & 0x10),
+                    robust_sigma=bool(fp.options & 0x40))
 
 
 def run_gpu(flagger, items, stream=None):
