@@ -71,11 +71,12 @@ CSRC = os.path.join(ROOT, "paper_1701_08197_amd", "csrc")
 
 
 def kernel_source_hash() -> str:
-    """sha256 (16 hex) over the HIP sources, in name order."""
+    """sha256 (16 hex) over the HIP sources and the C header, in name order."""
     import glob
     import hashlib
     h = hashlib.sha256()
-    for path in sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.hpp"))):
+    paths = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.hpp")))
+    for path in paths + [os.path.join(ROOT, "include", "lof.h")]:
         with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -664,8 +665,8 @@ def run_quality(args, cores):
     flagged, of each injected interferer flagged (recall), of clean samples
     flagged, and of the weak dispersed pulse left unflagged.  Methods: the full
     path (SumThreshold + SIR + history), SumThreshold alone, the simple
-    thresholder (median + 6 sigma, one level, no SIR, no history), and the
-    integrated pre-correlation mode."""
+    thresholder (median + 6 sigma, one level, no SIR, no history), the
+    integrated pre-correlation mode, and both with the stddev from the MAD."""
     import torch
     import paper_1701_08197_amd as P
     from paper_1701_08197_amd import _native as NAT
@@ -681,7 +682,9 @@ def run_quality(args, cores):
     methods = {"lof_full_path": dict(),
                "sumthreshold_only": dict(sir_eta_num=0, history_min=1 << 30),
                "simple_thresholder": dict(n_levels=1, n_levels_freq=0, sir_eta_num=0, history_min=1 << 30),
-               "integrated_mode": dict(options=P.LOF_OPT_INTEGRATED)}
+               "integrated_mode": dict(options=P.LOF_OPT_INTEGRATED),
+               "lof_robust_sigma": dict(options=P.LOF_OPT_ROBUST_SIGMA),
+               "integrated_robust_sigma": dict(options=P.LOF_OPT_INTEGRATED | P.LOF_OPT_ROBUST_SIGMA)}
     out = {}
     for name, kw in methods.items():
         fl = P.Flagger(P.default_params(max_streams=nb, max_channels=C, max_blocks_per_call=nb,
