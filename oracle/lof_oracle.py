@@ -20,6 +20,8 @@ the input is integer), favouring obviousness over speed:
 * history flagger ............................. Sec. 4.1 (pseudocode and Fig. "history")
 * integrated pre-correlation mode ............. Sec. 4 (integration paragraph, Fig. "integrate")
 * robust stddev from the MAD .................. Sec. 4.2 (statistics list)
+* 2-D flagging with partial integration ....... Sec. 4 (integration paragraph, the
+                                                 alternative method)
 
 Where the paper is silent or garbled, each function states the reading it
 implements.  Window sums are brute force
@@ -472,6 +474,50 @@ def integrated_block(x: np.ndarray, dtype: int, params: Params = Params(),
 
 
 ST_LEVELS_MAX = 7   # windows up to 64 samples
+
+
+# ------------------------------------------------- 2-D partial integration
+@dataclass
+class PartialResult:
+    flags: np.ndarray          # bool [C, T]: each sample takes its tile's flag
+    coarse: np.ndarray         # float32 [ceil(C/f_freq), ceil(T/f_time)] tile means
+    coarse_result: BlockResult  # the 2-D path on the coarse grid
+
+
+def integrate_tiles(p: np.ndarray, f_time: int, f_freq: int, exact: bool) -> np.ndarray:
+    """Tile means of the power (Sec. 4: partial integration in one or both
+    dimensions): tile (i, j) covers channels [i f_freq, (i+1) f_freq) and times
+    [j f_time, (j+1) f_time), clipped to the block, so edge tiles may hold fewer
+    samples; its value is the sum of its samples (exact integer, or an exact
+    float sum) divided by their number, rounded once to float32."""
+    C, T = p.shape
+    Cc, Tc = -(-C // f_freq), -(-T // f_time)
+    out = np.zeros((Cc, Tc), dtype=np.float32)
+    for i in range(Cc):
+        for j in range(Tc):
+            tile = p[i * f_freq:(i + 1) * f_freq, j * f_time:(j + 1) * f_time]
+            if exact:
+                total = sum(int(v) for v in tile.ravel().tolist())
+            else:
+                total = math.fsum(tile.ravel().tolist())
+            out[i, j] = np.float32(total / tile.size)
+    return out
+
+
+def partial_block(x: np.ndarray, dtype: int, params: Params = Params(), f_time: int = 1, f_freq: int = 1,
+                  history: History | None = None, stream_id: int = -1) -> PartialResult:
+    """2-D flagging with partial integration (Sec. 4, the alternative to the
+    integrated mode): integrate the power over tiles of f_freq channels x f_time
+    times (integrate_tiles), run the whole 2-D path of flag_block on the grid of
+    tile means (statistics, SumThreshold time then frequency, SIR, history per
+    row of tiles, keyed by the tile row), and give every sample its tile's flag."""
+    p = power(x, dtype)
+    C, T = p.shape
+    coarse = integrate_tiles(p, f_time, f_freq, is_exact(dtype))
+    r = flag_block(coarse, F32, params, history, stream_id)
+    rows = np.arange(C) // f_freq
+    cols = np.arange(T) // f_time
+    return PartialResult(r.flags[rows][:, cols], coarse, r)
 
 
 # ----------------------------------------------------------------------- sizing aid

@@ -670,3 +670,88 @@ def test_robust_sigma_finds_tones_the_classic_stddev_hides():
     assert not O.integrated_block(x, O.CI8, prm).channel_flags.any()
     r = O.integrated_block(x, O.CI8, O.Params(sir_eta_num=0, robust_sigma=True))
     assert r.channel_flags.nonzero()[0].tolist() == [5, 21, 40]
+
+
+# ------------------------------------------------- 2-D partial integration pins
+def test_partial_unit_tiles_equal_full_rate():
+    # tiles of one sample: the grid of means is the block itself (float32 power),
+    # so the result is the full-rate path's, history included
+    rng = np.random.default_rng(31)
+    x = synth.f32_power_block(rng, 24, 500)
+    prm = O.Params(history_min=1, history_len=4)
+    h1, h2 = O.History(prm), O.History(prm)
+    for _ in range(3):
+        r = O.partial_block(x, O.F32, prm, 1, 1, h1, 0)
+        f = O.flag_block(x, O.F32, prm, h2, 0)
+        assert (r.flags == f.flags).all()
+        assert h1.pending == h2.pending
+        h1.commit()
+        h2.commit()
+        x = x * np.float32(1.5)
+
+
+def test_partial_full_time_integration_is_the_integrated_spectrum_step():
+    # one tile per channel (f_time = T, T a power of two so the means are the exact
+    # spectrum / T): the 1 x C grid is flagged at level 1 along time and levels
+    # 2..64 along frequency, which is the integrated mode's spectrum flagging
+    # (Sec. 4) on a scaled spectrum, SIR included
+    rng = np.random.default_rng(5)
+    x = synth.ci8_block(rng, 64, 64, rfi=False)
+    x[11, :, 0] = np.clip(x[11, :, 0].astype(np.int64) + 60, -127, 127)   # a strong tone
+    prm = O.Params()
+    r = O.partial_block(x, O.CI8, prm, f_time=64, f_freq=1)
+    ri = O.integrated_block(x, O.CI8, prm)
+    assert ri.channel_flags.any()
+    assert (r.coarse[:, 0].astype(np.float64) * 64 == ri.spectrum).all()
+    assert (r.flags == ri.channel_flags[:, None]).all()
+
+
+def test_partial_full_frequency_integration_is_the_integrated_time_series_step():
+    # one tile per time (f_freq = C = 64): the grid is the all-channel time series
+    # / 64; when the integrated mode flags no channel its time series is the same
+    # sum, so the time flags agree
+    rng = np.random.default_rng(8)
+    x = synth.ci8_block(rng, 64, 1000, rfi=False)
+    x[:, 300:304, 0] = 60            # a broadband impulse, 4 samples wide
+    prm = O.Params()
+    ri = O.integrated_block(x, O.CI8, prm)
+    assert not ri.channel_flags.any() and ri.time_flags[300:304].all()
+    r = O.partial_block(x, O.CI8, prm, f_time=1, f_freq=64)
+    assert (r.coarse[0].astype(np.float64) * 64 == ri.series).all()
+    assert (r.flags == ri.time_flags[None, :]).all()
+
+
+def test_partial_tile_constant_block_with_ragged_tiles():
+    # power constant on every tile, edge tiles narrower (30 channels in tiles of 4,
+    # 50 times in tiles of 8): each tile mean is that constant whatever the tile's
+    # size, so the flags are the full-rate flags of the 8 x 7 grid of constants,
+    # spread over the tiles; the one strong tile is the ragged corner (2 x 2
+    # samples), flagged alone among 56 (a single impulse needs N >= 35)
+    rng = np.random.default_rng(12)
+    vals = rng.integers(1, 12, size=(8, 7)) ** 2
+    vals[7, 6] = 120 * 120
+    rows, cols = np.arange(30) // 4, np.arange(50) // 8
+    x = _ci8_from_power(vals[rows][:, cols])
+    prm = O.Params(sir_eta_num=0)
+    r = O.partial_block(x, O.CI8, prm, f_time=8, f_freq=4)
+    assert (r.coarse == vals.astype(np.float32)).all()
+    g = O.flag_block(vals.astype(np.float32), O.F32, prm)
+    assert g.flags[7, 6]
+    assert (r.flags == g.flags[rows][:, cols]).all()
+    assert r.flags[28:, 48:].all()
+
+
+@pytest.mark.parametrize("T,j0", [(128, 5), (125, 15)])
+def test_partial_broadband_impulse_hand_worked(T, j0):
+    # background power 1, power 400 in every channel over the times of tile column
+    # j0 (the last, 5 samples wide, when T = 125): the grid column of 400s is
+    # flagged along frequency (window of 4 tiles: mean 400 > 1 + 3.375 sigma,
+    # sigma = 399 * sqrt(15) / 16 ~ 96.6), a single flagged tile per row does not
+    # grow under SIR (floor(1/4) = 0), so exactly the impulse's times are flagged
+    C = 8
+    pw = np.ones((C, T), dtype=np.int64)
+    t = np.arange(T)
+    pw[:, t // 8 == j0] = 400
+    r = O.partial_block(_ci8_from_power(pw), O.CI8, O.Params(), f_time=8, f_freq=2)
+    assert r.coarse.shape == (4, 16)
+    assert (r.flags == (t // 8 == j0)[None, :]).all()
