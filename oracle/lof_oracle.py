@@ -22,6 +22,9 @@ the input is integer), favouring obviousness over speed:
 * robust stddev from the MAD .................. Sec. 4.2 (statistics list)
 * 2-D flagging with partial integration ....... Sec. 4 (integration paragraph, the
                                                  alternative method)
+* caller-supplied pre-flags ................... Sec. 4.2 (statistics of the unflagged
+                                                 samples), Sec. 2.1 (flagged samples
+                                                 leave the window sums)
 
 Where the paper is silent or garbled, each function states the reading it
 implements.  Window sums are brute force
@@ -351,17 +354,28 @@ class BlockResult:
 
 
 def flag_block(x: np.ndarray, dtype: int, params: Params = Params(),
-               history: History | None = None, stream_id: int = -1) -> BlockResult:
+               history: History | None = None, stream_id: int = -1,
+               preflags: np.ndarray | None = None) -> BlockResult:
     """The whole per-block hot path: power -> median, stddev -> thresholds ->
     SumThreshold time then frequency -> SIR time then frequency -> history flagger
-    (pending values are staged in ``history``; call ``history.commit``)."""
+    (pending values are staged in ``history``; call ``history.commit``).
+
+    ``preflags`` (bool [C, T]) marks samples flagged before the flagger runs
+    (Sec. 4.2: the statistics are those of the unflagged samples): they leave the
+    median and stddev (with none left, both are 0), start flagged in SumThreshold
+    (so they leave every window's sum and count) and stay flagged."""
     exact = is_exact(dtype)
     p = power(x, dtype)
     C, T = p.shape
-    med = block_median(p)
-    sd = block_mad_sigma(p, exact) if params.robust_sigma else block_stddev(p, exact)
+    pre = None if preflags is None else np.asarray(preflags, dtype=bool)
+    live = p if pre is None else p[~pre]
+    if live.size == 0:
+        med, sd = 0.0, 0.0
+    else:
+        med = block_median(live)
+        sd = block_mad_sigma(live, exact) if params.robust_sigma else block_stddev(live, exact)
     th = thresholds(med, sd, params)
-    st = sumthreshold_block(p, th, params, exact)
+    st = sumthreshold_block(p, th, params, exact, mask=pre)
     sm = sir_block(st, params)
     hrows = np.zeros(C, dtype=bool)
     pend = [None] * C

@@ -755,3 +755,102 @@ def test_partial_broadband_impulse_hand_worked(T, j0):
     r = O.partial_block(_ci8_from_power(pw), O.CI8, O.Params(), f_time=8, f_freq=2)
     assert r.coarse.shape == (4, 16)
     assert (r.flags == (t // 8 == j0)[None, :]).all()
+
+
+# --------------------------------------------------------- caller-supplied pre-flags
+def test_preflags_none_equal_no_preflags():
+    x = synth.ci8_block(np.random.default_rng(40), 16, 300)
+    a = O.flag_block(x, O.CI8)
+    b = O.flag_block(x, O.CI8, preflags=np.zeros((16, 300), dtype=bool))
+    assert (a.flags == b.flags).all() and a.median == b.median and a.stddev == b.stddev
+
+
+@pytest.mark.parametrize("robust", [False, True])
+def test_preflags_leave_the_statistics(robust):
+    rng = np.random.default_rng(41)
+    x = synth.ci8_block(rng, 12, 500)
+    pre = rng.random((12, 500)) < 0.3
+    r = O.flag_block(x, O.CI8, O.Params(robust_sigma=robust), preflags=pre)
+    live = O.power(x, O.CI8)[~pre].astype(np.float64)
+    assert r.median == np.median(live)
+    sd = 1.4826 * np.median(np.abs(live - np.median(live))) if robust else np.std(live)
+    assert r.stddev == pytest.approx(sd, rel=1e-12)
+    assert r.flags[pre].all()
+
+
+def test_preflagged_rows_are_removed_rows():
+    # frequency levels and SIR off: rows are independent along time, so
+    # pre-flagging whole rows is the same as flagging the block without them
+    rng = np.random.default_rng(42)
+    x = synth.ci8_block(rng, 20, 700)
+    rows = np.zeros(20, dtype=bool)
+    rows[[1, 5, 6, 17]] = True
+    prm = O.Params(n_levels_freq=0, sir_eta_num=0)
+    r = O.flag_block(x, O.CI8, prm, preflags=np.repeat(rows[:, None], 700, axis=1))
+    q = O.flag_block(x[~rows], O.CI8, prm)
+    assert r.flags[rows].all()
+    assert (r.flags[~rows] == q.flags).all() and r.thresholds == q.thresholds
+
+
+def test_preflagging_a_strong_burst_reveals_a_weak_outlier():
+    # power 1 everywhere, a burst of 10^4 over 10 % of the block and one sample of
+    # power 16: the burst's share of the stddev hides the outlier; with the burst
+    # pre-flagged the remaining samples have median 1 and stddev 15/sqrt(N), and
+    # the lone outlier is flagged (N >= 35)
+    C, T = 10, 100
+    pw = np.ones((C, T), dtype=np.int64)
+    pw[:, 40:50] = 100 * 100
+    pw[3, 80] = 16
+    x = _ci8_from_power(pw)
+    prm = O.Params(sir_eta_num=0)
+    plain = O.flag_block(x, O.CI8, prm)
+    assert not plain.flags[3, 80]
+    pre = np.zeros((C, T), dtype=bool)
+    pre[:, 40:50] = True
+    r = O.flag_block(x, O.CI8, prm, preflags=pre)
+    n = C * T - pre.sum()
+    assert r.median == 1.0 and r.stddev == pytest.approx(15 * np.sqrt(n - 1) / n, rel=1e-12)
+    expect = pre.copy()
+    expect[3, 80] = True
+    assert (r.flags == expect).all()
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_preflags_tiny_exhaustive_vs_rational_bruteforce(seed):
+    # SumThreshold from a random initial mask, window by window in exact
+    # rational arithmetic, with the thresholds of the unflagged samples
+    rng = np.random.default_rng(2000 + seed)
+    C, T = int(rng.integers(1, 6)), int(rng.integers(2, 9))
+    x = rng.integers(-6, 7, size=(C, T, 2)).astype(np.int8)
+    x[rng.integers(0, C), rng.integers(0, T), 0] = 50
+    pre = rng.random((C, T)) < 0.25
+    prm = O.Params(start_threshold=float(rng.choice([0.5, 1.0, 2.0])), sir_eta_num=0)
+    r = O.flag_block(x, O.CI8, prm, preflags=pre)
+    p = O.power(x, O.CI8)
+    live = sorted(int(v) for v in p[~pre])
+    if live:
+        n = len(live)
+        med = Fraction(live[n // 2]) if n % 2 else Fraction(live[n // 2 - 1] + live[n // 2], 2)
+        assert r.median == float(med)
+    th = r.thresholds
+
+    def run(rows, masks):
+        out = []
+        for vals, m in zip(rows, masks):
+            m = list(m)
+            for k in range(prm.n_levels):
+                I = 1 << k
+                if I > len(vals):
+                    break
+                nm = list(m)
+                for s in range(len(vals) - I + 1):
+                    live_w = [vals[j] for j in range(s, s + I) if not m[j]]
+                    if live_w and Fraction(sum(live_w)) > len(live_w) * Fraction(th[k]):
+                        for j in range(s, s + I):
+                            nm[j] = True
+                m = nm
+            out.append(m)
+        return np.array(out, dtype=bool)
+    mt = run([[int(v) for v in row] for row in p], pre.tolist())
+    mf = run([[int(v) for v in col] for col in p.T], mt.T.tolist()).T
+    assert (r.st_mask == mf).all()
