@@ -25,7 +25,10 @@ Other workloads (--workload): scaling (run time against the number of
 stations, with and without SIR), config0 (one complex64 block, latency),
 batched (4096 uneven float32 blocks: per-block calls, one batched call,
 autotuned, hipGraph), config3a (beam-formed Stokes I), config3b (visibility
-amplitudes), serve (streaming service).  The float workloads also report the
+amplitudes), serve (streaming service), integrated (the integrated
+pre-correlation mode on the default workload), partial (2-D flagging with
+partial integration on the default workload), quality (flag quality against
+the injected truth).  The float workloads also report the
 flag mismatch rate against the CPU reference on a sample of their blocks.
 """
 from __future__ import annotations
@@ -349,6 +352,81 @@ def run_second(args, cores, integrated=False):
         "gen_s": round(t_gen, 1),
     }
     return out
+
+
+# ------------------------------------------------------------------ partial integration
+def _partial_one(args):
+    b, pt, pf = args
+    import oracle.lof_oracle as O
+    return O.partial_block(synth.config1_block(b, 0), O.CI8, O.Params(), pt, pf).flags
+
+
+def run_partial(args, cores):
+    """The default workload's second flagged with 2-D partial integration (tiles
+    of partial_freq channels x partial_time times; Sec. 4, the alternative
+    method): whole-job throughput in samples of the caller's blocks, and the
+    flag mismatch against the CPU reference on sampled blocks (history off)."""
+    import torch
+    import paper_1701_08197_amd as P
+    from paper_1701_08197_amd import _native as NAT
+    nb, pt, pf = args.blocks, args.partial_time, args.partial_freq
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    secs = resident_seconds(nb, args.seconds, cores, dev)
+    t_gen = time.perf_counter() - t_gen
+    flags = torch.empty((nb, C, T), dtype=torch.uint8, device=dev)
+    prm = P.default_params(max_streams=nb, max_channels=C, max_blocks_per_call=nb, max_samples_per_call=nb * C * T,
+                           partial_time=pt, partial_freq=pf)
+    fl = P.Flagger(prm)
+    tables = [block_table(d, flags, nb, NAT.LOF_CI8) for d in secs]
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+    for k in range(args.warmup):
+        fl.flag_blocks_raw(tables[k % len(tables)], nb, sh)
+        fl.history_update(None, sh)
+    torch.cuda.synchronize()
+    K = args.steps
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    t0 = time.perf_counter()
+    for k in range(K):
+        evs[k][0].record(stream)
+        if fl.flag_blocks_raw(tables[(args.warmup + k) % len(tables)], nb, sh) != 0:
+            raise RuntimeError("lof_flag_blocks failed")
+        fl.history_update(None, sh)
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fl.close()
+    progress(f"{K} timed steps done")
+    call_ms = [a.elapsed_time(b) for a, b in evs]
+    samples = nb * C * T
+    ms = wall * 1e3 / K
+    Cc, Tc = -(-C // pf), -(-T // pt)
+    # input once + one flag byte per sample + the tile rows' history rings
+    alg = samples * 3 + nb * Cc * (min(args.warmup + K, prm.history_len) + 1) * 8
+    cmean = statistics.mean(call_ms)
+    # mismatch on sampled blocks of second 0, history off
+    fr = P.Flagger(P.default_params(max_streams=1, max_channels=C, max_blocks_per_call=nb,
+                                    max_samples_per_call=nb * C * T, partial_time=pt, partial_freq=pf))
+    fr.flag_blocks_raw(block_table(secs[0], flags, nb, NAT.LOF_CI8, with_streams=False), nb, sh)
+    torch.cuda.synchronize()
+    fr.close()
+    rng = np.random.default_rng(7)
+    sample = sorted(rng.choice(nb, size=min(nb, max(1, args.check_blocks // 8)), replace=False).tolist())
+    with mp.get_context("spawn").Pool(min(cores, len(sample))) as pool:
+        ref = pool.map(_partial_one, [(b, pt, pf) for b in sample])
+    bad = sum(int(np.count_nonzero(flags[b].cpu().numpy().astype(bool) != r)) for b, r in zip(sample, ref))
+    tot = len(sample) * C * T
+    return {"metric": "flagged Gsamples/s, 2-D partial integration", "unit": "Gsamples/s",
+            "value": round(samples / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 4),
+            "workload": f"the default second (6144 blocks of 64 x 3072 complex int8), tiles of {pf} channels x "
+                        f"{pt} times -> {Cc} x {Tc} grid per block, history on the grid's rows",
+            "call_ms_mean": round(cmean, 4), "p99_call_ms": round(pct(call_ms, 0.99), 3),
+            "alg_bytes_per_sample": round(alg / samples, 4),
+            "hbm_frac": round(alg / (cmean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "mismatch_vs_oracle": {"rate": bad / tot, "mismatches": bad, "samples": tot,
+                                   "blocks_checked": len(sample)},
+            "gen_s": round(t_gen, 1)}
 
 
 # ------------------------------------------------------------------ E6: scaling with stations
@@ -790,10 +868,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--workers", type=int, default=0)
     ap.add_argument("--workload", default="second",
-                    choices=["second", "integrated", "scaling", "config0", "batched", "config3a", "config3b",
+                    choices=["second", "integrated", "partial", "scaling", "config0", "batched", "config3a", "config3b",
                              "serve", "quality"])
     ap.add_argument("--blocks2", type=int, default=4096)
     ap.add_argument("--quality-blocks", type=int, default=256)
+    ap.add_argument("--partial-time", type=int, default=16, help="partial workload: times per tile")
+    ap.add_argument("--partial-freq", type=int, default=4, help="partial workload: channels per tile")
     ap.add_argument("--check-blocks", type=int, default=512, help="blocks compared with the CPU reference")
     ap.add_argument("--slots", type=int, default=4096)
     ap.add_argument("--speedups", default="10,50,100,200,300,400,600")
@@ -808,7 +888,8 @@ def main():
     runners = {"scaling": run_scaling, "config0": run_config0, "batched": run_batched,
                "integrated": lambda a, c: run_second(a, c, integrated=True), "quality": run_quality,
                "config3a": lambda a, c: run_uniform_float(a, c, "config3a"),
-               "config3b": lambda a, c: run_uniform_float(a, c, "config3b"), "serve": run_serve}
+               "config3b": lambda a, c: run_uniform_float(a, c, "config3b"), "serve": run_serve,
+               "partial": run_partial}
     if args.workload in runners:
         print(json.dumps(runners[args.workload](args, workers)), flush=True)
         return

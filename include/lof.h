@@ -99,6 +99,19 @@ typedef enum {
                                             input stays exact (the deviations are
                                             integers or half-integers)                 */
 
+#define LOF_OPT_PREFLAGGED 0x80u         /* caller-supplied pre-flags: on entry each block's
+                                            flag bytes hold a mask (nonzero = flagged, e.g.
+                                            known-bad samples or an earlier flagger's
+                                            output); those samples leave the median and
+                                            stddev (Sec. 4.2: statistics of the unflagged
+                                            samples; none left: median and stddev 0),
+                                            start flagged in SumThreshold, so they leave
+                                            every window's sum and count (Sec. 2.1), and
+                                            stay flagged; the flag bytes are then
+                                            overwritten with the result.  Not with
+                                            LOF_OPT_INTEGRATED or partial integration, nor
+                                            in lof_autotune (LOF_ERR_INVALID).          */
+
 /* Phases of the path, in launch order (lof_phase_times) */
 #define LOF_PHASE_STATS 0        /* power, median, stddev, thresholds (Sec. 2.1, 4.2)   */
 #define LOF_PHASE_ST_TIME 1      /* SumThreshold along time (Sec. 2.1)                  */
@@ -139,6 +152,22 @@ typedef struct {
                                   (sized by the maxima above); 0 = 4              */
   int64_t max_samples_per_call;/* sum of C*T over one lof_flag_blocks call            */
   uint32_t options;            /* LOF_OPT_* bits                                      */
+  int32_t partial_time;        /* 2-D flagging with partial integration (Sec. 4, the
+                                  alternative to the integrated mode): times per tile,
+                                  0 or 1 = none; 1..65536                            */
+  int32_t partial_freq;        /* channels per tile, 0 or 1 = none; 1..1024.  With
+                                  either above 1 every block is integrated into tile
+                                  means (sum of the tile's powers / its sample count,
+                                  rounded once to float32; tiles at the block's end
+                                  hold fewer samples), the whole path of this header
+                                  runs on the grid of means as float32 input (history
+                                  keyed by (stream, row of tiles)), and every sample
+                                  takes its tile's flag.  The stats entry then holds
+                                  the grid's median, stddev and thresholds, n_flagged
+                                  counts samples of the block, history_flagged_rows
+                                  rows of tiles.  Not with LOF_OPT_INTEGRATED or
+                                  LOF_OPT_GRAPH, nor in lof_autotune or
+                                  lof_flag_blocks_static (LOF_ERR_INVALID).        */
   int32_t _reserved1;
 } lof_params;
 

@@ -22,6 +22,7 @@ LOF_OPT_PHASE_TIMING = 0x8
 LOF_OPT_SIR_PROSE = 0x10
 LOF_OPT_INTEGRATED = 0x20
 LOF_OPT_ROBUST_SIGMA = 0x40
+LOF_OPT_PREFLAGGED = 0x80
 # phases of lof_phase_times, in launch order
 PHASES = ("stats", "sumthreshold_time", "sumthreshold_freq", "sir_time", "sir_freq", "history_write")
 LOF_N_PHASES = len(PHASES)
@@ -51,6 +52,8 @@ class LofParams(ctypes.Structure):
         ("call_slots", ctypes.c_int32),
         ("max_samples_per_call", ctypes.c_int64),
         ("options", ctypes.c_uint32),
+        ("partial_time", ctypes.c_int32),
+        ("partial_freq", ctypes.c_int32),
         ("_reserved1", ctypes.c_int32),
     ]
 

@@ -26,6 +26,7 @@
 #include "lof.h"
 #include "lof_kernel_table.hpp"
 #include "lof_integrated.hpp"
+#include "lof_partial.hpp"
 #include "lof_post.hpp"
 #include "lof_kernels.hpp"
 
@@ -122,6 +123,18 @@ struct Slot {
   bool timed = false;             // events of a call not yet added to the totals
 };
 
+// partial integration (lof_params.partial_time / partial_freq): per call slot, the
+// grid of tile means and tile flags of every block, their descriptor tables and
+// the statistics of the grids
+struct PSlot {
+  Slot s;                                  // the grids' call: descriptor table and scratch
+  lofk::PartialBlock* d_part = nullptr;    // per caller block: block and its grid
+  lofk::PartialBlock* h_part = nullptr;    // pinned
+  float* d_coarse = nullptr;
+  uint8_t* d_cflags = nullptr;
+  lof_block_stats* d_cstats = nullptr;
+};
+
 int time_bucket(int T) { return T <= 1024 ? 0 : (T <= 2048 ? 1 : (T <= 3072 ? 2 : (T <= 4096 ? 3 : 4))); }
 int lanes_index(int L) { return L == 32 ? 0 : (L == 48 ? 1 : 2); }
 bool lanes_allowed(int L, int bucket) {
@@ -134,7 +147,7 @@ constexpr int NVAR = 6;   // time layouts: (integer, float) x (32, 48, 64 lanes)
 // kernels, for occupancy lookups
 enum KernId {
   K_STATS = 0, K_TIME = 2, K_FREQ = 8, K_SIRT = 10, K_SIRF = 13, K_FINAL = 14, K_PROSE = 16, K_INTEG = 18, K_POST = 20,
-  NKERN = 22
+  K_STATS_PRE = 22, K_TIME_PRE = 24, NKERN = 30
 };
 int variant_lanes(int v) { return v % 3 == 0 ? 32 : (v % 3 == 1 ? 48 : 64); }
 
@@ -169,6 +182,12 @@ struct lof_ctx {
   std::vector<DevBlock> tmp;
   std::vector<int> order;
   double phase_ms[LOF_N_PHASES] = {};   // LOF_OPT_PHASE_TIMING totals since the last read
+  // partial integration: tile shape, grid capacity per call, slots, grid blocks
+  bool partial = false;
+  int pt = 1, pf = 1;
+  size_t coarse_cap = 0;
+  std::vector<PSlot> pslot;
+  std::vector<lof_block> ctmp;
   int32_t phase_calls = 0;
   const char* err = "no error";
 };
@@ -234,6 +253,13 @@ const char* check_params(const lof_params* p) {
   if (p->max_blocks_per_call < 1) return "max_blocks_per_call must be >= 1";
   if (p->max_samples_per_call < 1) return "max_samples_per_call must be >= 1";
   if (p->call_slots < 0 || p->call_slots > MAX_SLOTS) return "call_slots must be in 0..65536";
+  if (p->partial_time < 0 || p->partial_time > lofk::PART_MAX_TIME) return "partial_time must be in 0..4096";
+  if (p->partial_freq < 0 || p->partial_freq > LOF_MAX_CHANNELS) return "partial_freq must be in 0..1024";
+  if ((p->partial_time > 1 || p->partial_freq > 1) &&
+      (p->options & (LOF_OPT_INTEGRATED | LOF_OPT_GRAPH | LOF_OPT_PREFLAGGED)))
+    return "partial integration does not combine with LOF_OPT_INTEGRATED, LOF_OPT_GRAPH or LOF_OPT_PREFLAGGED";
+  if ((p->options & LOF_OPT_PREFLAGGED) && (p->options & LOF_OPT_INTEGRATED))
+    return "LOF_OPT_PREFLAGGED does not combine with LOF_OPT_INTEGRATED";
   return nullptr;
 }
 
@@ -256,6 +282,9 @@ const void* kernel_of(int k) {
   if (k == K_PROSE || k == K_PROSE + 1) return lofk::kernel_prose(k == K_PROSE + 1);
   if (k == K_INTEG || k == K_INTEG + 1) return lofk::kernel_integrated(k == K_INTEG);
   if (k == K_POST || k == K_POST + 1) return lofk::kernel_post(k == K_POST);
+  if (k == K_STATS_PRE || k == K_STATS_PRE + 1) return lofk::kernel_stats_pre(k == K_STATS_PRE);
+  if (k >= K_TIME_PRE && k < K_TIME_PRE + 6)
+    return lofk::kernel_time_pre(k < K_TIME_PRE + 3, variant_lanes(k - K_TIME_PRE));
   return lofk::kernel_final(k == K_FINAL);
 }
 
@@ -272,6 +301,19 @@ void free_slot(Slot& s) {
     if (e) (void)hipEventDestroy(e);
   s = Slot();
 }
+
+void free_pslot(PSlot& p) {
+  free_slot(p.s);
+  if (p.d_part) (void)hipFree(p.d_part);
+  if (p.h_part) (void)hipHostFree(p.h_part);
+  if (p.d_coarse) (void)hipFree(p.d_coarse);
+  if (p.d_cflags) (void)hipFree(p.d_cflags);
+  if (p.d_cstats) (void)hipFree(p.d_cstats);
+  p = PSlot();
+}
+
+int ceil_div(int a, int b) { return (a + b - 1) / b; }
+int64_t round16(int64_t x) { return (x + 15) & ~(int64_t)15; }
 
 bool alloc_slot(Slot& s, int max_blocks, int max_channels, size_t mask_words, bool timing, bool prose) {
   if (timing)
@@ -359,6 +401,12 @@ lof_status validate(lof_ctx* c, const lof_block* blocks, int32_t n, bool check_i
     for (int i = 0; i < n; ++i)
       if (blocks[i].n_times > lofk::INTEG_MAX_T) return fail(c, LOF_ERR_INVALID, "integrated mode: n_times > 16384");
   if (words > c->mask_words) return fail(c, LOF_ERR_CAPACITY, "mask scratch too small");
+  if (c->partial) {
+    size_t cells = 0;
+    for (int i = 0; i < n; ++i)
+      cells += (size_t)ceil_div(blocks[i].n_channels, c->pf) * (size_t)round16(ceil_div(blocks[i].n_times, c->pt));
+    if (cells > c->coarse_cap) return fail(c, LOF_ERR_CAPACITY, "partial integration: tile grids too large");
+  }
   return LOF_OK;
 }
 
@@ -460,14 +508,16 @@ void enqueue(lof_ctx* c, const lof_tuning& t, Slot& s, const int* counts, int n,
       off += kcnt;
       continue;
     }
-    launch(c, t, K_STATS + kind, LOF_PHASE_STATS, dk, kcnt, 0, s, nc, st, P);
+    const bool pre = (c->prm.options & LOF_OPT_PREFLAGGED) != 0;
+    launch(c, t, (pre ? K_STATS_PRE : K_STATS) + kind, LOF_PHASE_STATS, dk, kcnt, 0, s, nc, st, P);
     int mt[3] = {0, 0, 0};
     for (int j = 0, voff = 0; j < 3; voff += counts[3 * kind + j], ++j) {
       const int cnt = counts[3 * kind + j];
       if (!cnt) continue;
       const int L = variant_lanes(j);
       mt[j] = max_chunks(hk + voff, cnt, [&](const DevBlock& b) { return lofk::time_chunks(b.C, b.T, L); });
-      launch(c, t, K_TIME + 3 * kind + j, LOF_PHASE_ST_TIME, dk + voff, cnt, mt[j], s, nc, st, P);
+      launch(c, t, (pre ? K_TIME_PRE : K_TIME) + 3 * kind + j, LOF_PHASE_ST_TIME, dk + voff, cnt, mt[j], s, nc, st,
+             P);
     }
     const int mf = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::freq_chunks(integer, b.C, b.T); });
     launch(c, t, K_FREQ + kind, LOF_PHASE_ST_FREQ, dk, kcnt, mf, s, nc, st, P);
@@ -517,6 +567,88 @@ bool harvest_timing(lof_ctx* c, Slot& s) {
   return true;
 }
 
+// one lof_flag_blocks call with partial integration: tile means of every block,
+// the whole path on the grids (as float32 blocks, history keyed by row of tiles),
+// then every sample of a block takes its tile's flag
+lof_status flag_partial(lof_ctx* c, const lof_block* blocks, int32_t n, hipStream_t st, lof_block_stats* stats,
+                        bool autocommit) {
+  Slot& s = c->slot[c->next];
+  PSlot& ps = c->pslot[c->next];
+  c->next = (c->next + 1) % (int)c->slot.size();
+  if (s.used) {
+    // the slot's previous call must be done before its tables and grids are reused
+    if (hipEventSynchronize(s.ev) != hipSuccess) return fail(c, LOF_ERR_DEVICE, "hipEventSynchronize failed");
+    if (!harvest_timing(c, ps.s)) return fail(c, LOF_ERR_DEVICE, "event timing failed");
+  }
+  int64_t off = 0;
+  int max_items = 1, max_rows = 1;
+  bool kinds[2] = {false, false};
+  for (int i = 0; i < n; ++i) {
+    const lof_block& b = blocks[i];
+    lofk::PartialBlock& pb = ps.h_part[i];
+    DevBlock& d = pb.fine;
+    d = DevBlock();
+    d.data = b.data;
+    d.flags = b.flags;
+    d.dstride = b.data_row_stride;
+    d.fstride = b.flag_row_stride;
+    d.C = b.n_channels;
+    d.T = b.n_times;
+    d.dtype = b.dtype;
+    d.stream_id = b.stream_id;
+    d.out_idx = i;
+    const size_t es = elem_size(b.dtype);
+    d.aligned = (((uintptr_t)b.data % 16) == 0 && ((size_t)b.data_row_stride * es) % 16 == 0) ? 1 : 0;
+    d.faligned = (((uintptr_t)b.flags % 16) == 0 && (b.flag_row_stride % 16) == 0) ? 1 : 0;
+    pb.Cc = ceil_div(b.n_channels, c->pf);
+    pb.Tc = ceil_div(b.n_times, c->pt);
+    pb.cstride = round16(pb.Tc);
+    pb.coarse = ps.d_coarse + off;
+    pb.cflags = ps.d_cflags + off;
+    pb.ff = c->pf;
+    pb.ft = c->pt;
+    lof_block& cb = c->ctmp[i];
+    cb.data = pb.coarse;
+    cb.flags = pb.cflags;
+    cb.data_row_stride = pb.cstride;
+    cb.flag_row_stride = pb.cstride;
+    cb.n_channels = pb.Cc;
+    cb.n_times = pb.Tc;
+    cb.dtype = LOF_F32;
+    cb.stream_id = b.stream_id;
+    off += (int64_t)pb.Cc * pb.cstride;
+    max_items = std::max(max_items, lofk::part_items(pb.Cc, pb.Tc, pb.ft));
+    max_rows = std::max(max_rows, lofk::part_spread_chunks(b.n_channels));
+    kinds[b.dtype == LOF_CI8 ? 0 : 1] = true;
+  }
+  if (hipMemcpyAsync(ps.d_part, ps.h_part, sizeof(lofk::PartialBlock) * n, hipMemcpyHostToDevice, st) != hipSuccess)
+    return fail(c, LOF_ERR_DEVICE, "descriptor upload failed");
+  const lofk::PartialBlock* dpart = ps.d_part;
+  int a_n = n, a_items = max_items, a_rows = max_rows;
+  lof_block_stats* a_stats = stats;
+  const lof_block_stats* a_cstats = ps.d_cstats;
+  for (int kind = 0; kind < 2; ++kind) {
+    if (!kinds[kind]) continue;
+    void* args[] = {&dpart, &a_n, &a_items, &a_stats};
+    (void)hipLaunchKernel(lofk::kernel_partial_integrate(kind == 0), dim3(n * max_items), dim3(lofk::WG), args, 0, st);
+  }
+  int counts[NVAR];
+  build_table(c->order.data(), c->tune, c->ctmp.data(), n, ps.s, counts, true);
+  if (hipMemcpyAsync(ps.s.d_desc, ps.s.h_desc, sizeof(DevBlock) * n, hipMemcpyHostToDevice, st) != hipSuccess)
+    return fail(c, LOF_ERR_DEVICE, "descriptor upload failed");
+  const bool timing = (c->prm.options & LOF_OPT_PHASE_TIMING) != 0;
+  enqueue(c, c->tune, ps.s, counts, n, ps.d_cstats, st, autocommit, timing);
+  {
+    void* args[] = {&dpart, &a_n, &a_rows, &a_cstats, &a_stats};
+    (void)hipLaunchKernel(lofk::kernel_partial_spread(), dim3(n * max_rows), dim3(lofk::WG), args, 0, st);
+  }
+  if (hipGetLastError() != hipSuccess) return fail(c, LOF_ERR_DEVICE, "kernel launch failed");
+  ps.s.timed = timing && ps.s.ntev >= 2;
+  if (hipEventRecord(s.ev, st) != hipSuccess) return fail(c, LOF_ERR_DEVICE, "hipEventRecord failed");
+  s.used = true;
+  return LOF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -546,6 +678,7 @@ lof_status lof_destroy(lof_ctx* c) {
   if (!c) return LOF_OK;
   DevGuard g(c->dev);
   for (auto& s : c->slot) free_slot(s);
+  for (auto& p : c->pslot) free_pslot(p);
   free_slot(c->gslot);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -604,6 +737,28 @@ lof_status lof_create(const lof_params* params, int hip_device, lof_ctx** out) {
   c->slot.resize(params->call_slots > 0 ? params->call_slots : NSLOT);
   for (size_t i = 0; ok && i < c->slot.size(); ++i)
     ok = alloc_slot(c->slot[i], params->max_blocks_per_call, params->max_channels, c->mask_words, timing, prose);
+  c->partial = params->partial_time > 1 || params->partial_freq > 1;
+  if (ok && c->partial) {
+    c->pt = std::max(1, params->partial_time);
+    c->pf = std::max(1, params->partial_freq);
+    // tile cells of one call, rows padded to 16: per block at most
+    // C (T + 15) and (C/pf + 1) (T/pt + 16); the sum of T is at most the samples
+    const size_t S = (size_t)params->max_samples_per_call, B = (size_t)params->max_blocks_per_call;
+    const size_t M = (size_t)params->max_channels;
+    const size_t cap1 = S + 15 * B * M;
+    const size_t cap2 = S / ((size_t)c->pf * c->pt) + 16 * B * (M / c->pf + 1) + S / c->pt + 16 * B + 64;
+    c->coarse_cap = std::min(cap1, cap2);
+    c->pslot.resize(c->slot.size());
+    for (size_t i = 0; ok && i < c->pslot.size(); ++i) {
+      PSlot& p = c->pslot[i];
+      ok = alloc_slot(p.s, params->max_blocks_per_call, params->max_channels, c->mask_words, timing, prose) &&
+           hipMalloc(&p.d_part, sizeof(lofk::PartialBlock) * B) == hipSuccess &&
+           hipHostMalloc(&p.h_part, sizeof(lofk::PartialBlock) * B, hipHostMallocDefault) == hipSuccess &&
+           hipMalloc(&p.d_coarse, sizeof(float) * c->coarse_cap) == hipSuccess &&
+           hipMalloc(&p.d_cflags, c->coarse_cap) == hipSuccess &&
+           hipMalloc(&p.d_cstats, sizeof(lof_block_stats) * B) == hipSuccess;
+    }
+  }
   if (ok && (params->options & LOF_OPT_GRAPH)) {
     ok = alloc_slot(c->gslot, params->max_blocks_per_call, params->max_channels, c->mask_words, false, prose) &&
          hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
@@ -630,6 +785,7 @@ lof_status lof_create(const lof_params* params, int hip_device, lof_ctx** out) {
   c->seen.assign(params->max_streams, -1);
   c->tmp.resize(params->max_blocks_per_call);
   c->order.resize(params->max_blocks_per_call);
+  if (c->partial) c->ctmp.resize(params->max_blocks_per_call);
   *out = c;
   return LOF_OK;
 }
@@ -683,6 +839,7 @@ lof_status lof_flag_blocks(lof_ctx* c, const lof_block* blocks, int32_t n, void*
     return LOF_OK;
   }
 
+  if (c->partial) return flag_partial(c, blocks, n, st, stats, autocommit);
   Slot& s = c->slot[c->next];
   c->next = (c->next + 1) % (int)c->slot.size();
   if (s.used) {
@@ -720,6 +877,9 @@ lof_status lof_autotune(lof_ctx* c, const lof_block* blocks, int32_t n, void* hi
                         lof_tuning* out) {
   if (!c) return LOF_ERR_INVALID;
   if (n < 0 || reps < 1) return fail(c, LOF_ERR_INVALID, "n < 0 or reps < 1");
+  if (c->partial) return fail(c, LOF_ERR_INVALID, "lof_autotune does not run with partial integration");
+  if (c->prm.options & LOF_OPT_PREFLAGGED)
+    return fail(c, LOF_ERR_INVALID, "lof_autotune does not run with LOF_OPT_PREFLAGGED (tuning runs overwrite flags)");
   if (n > 0 && !blocks) return fail(c, LOF_ERR_INVALID, "blocks is NULL");
   if (n > 0) {
     const lof_status vs = validate(c, blocks, n, false);
@@ -873,6 +1033,8 @@ lof_status lof_phase_times(lof_ctx* c, double* ms, int32_t* n_calls) {
   DevGuard g(c->dev);
   for (auto& s : c->slot)
     if (!harvest_timing(c, s)) return fail(c, LOF_ERR_DEVICE, "event timing failed");
+  for (auto& p : c->pslot)
+    if (!harvest_timing(c, p.s)) return fail(c, LOF_ERR_DEVICE, "event timing failed");
   for (int p = 0; p < LOF_N_PHASES; ++p) {
     ms[p] = c->phase_ms[p];
     c->phase_ms[p] = 0.0;
@@ -905,6 +1067,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 lof_status lof_flag_blocks_static(const lof_params* params, int hip_device, const lof_block* blocks,
                                   int32_t n_blocks, void* hip_stream, lof_block_stats* stats) {
   if (const char* m = check_params(params)) return static_fail(LOF_ERR_INVALID, m);
+  if (params->partial_time > 1 || params->partial_freq > 1)
+    return static_fail(LOF_ERR_INVALID, "no partial integration here");
   if (n_blocks < 0) return static_fail(LOF_ERR_INVALID, "n_blocks < 0");
   if (n_blocks == 0) return LOF_OK;
   if (!blocks) return static_fail(LOF_ERR_INVALID, "blocks is NULL");

@@ -324,6 +324,26 @@ constexpr int TILE_ELEMS = NW * 64 * 32;   // frequency slab: (G*32 channels) x 
 constexpr int TILE_PAD = 1024;             // one padding element per slab row (<= 1024 rows)
 constexpr int TILE_WORDS = 1024;           // mask words of one frequency slab
 
+// caller-supplied pre-flags (LOF_OPT_PREFLAGGED) of the nv <= 8 samples of a row
+// from t0: bit j set when the flag byte of t0 + j is nonzero
+template <bool PRE>
+__device__ __forceinline__ uint32_t pre8(const DevBlock& b, int row, int t0, int nv) {
+  if constexpr (!PRE) {
+    return 0u;
+  } else {
+    const GLB uint8_t* fb = gp<const uint8_t>(b.flags) + (int64_t)row * b.fstride + t0;
+    uint32_t m = 0;
+    if (b.faligned && nv == 8 && (t0 & 7) == 0) {
+      const uint64_t w = *(const GLB uint64_t*)fb;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) m |= ((w >> (8 * j)) & 0xffull) ? (1u << j) : 0u;
+    } else {
+      for (int j = 0; j < nv; ++j) m |= fb[j] ? (1u << j) : 0u;
+    }
+    return m;
+  }
+}
+
 // Shared memory of each kernel: only what that kernel's phase uses.
 template <bool INT>
 struct SmStats {
@@ -337,6 +357,7 @@ struct SmStats {
   unsigned long long red_u[2][NW];
   uint32_t scan[NW];
   uint32_t sel[4];
+  uint32_t nlive;                            // samples not pre-flagged
   double median, sigma;
 };
 

@@ -4,6 +4,9 @@
 
 namespace lofk {
 const void* kernel_stats(bool integer) {
-  return integer ? (const void*)lof_stats_kernel<true> : (const void*)lof_stats_kernel<false>;
+  return integer ? (const void*)lof_stats_kernel<true, false> : (const void*)lof_stats_kernel<false, false>;
+}
+const void* kernel_stats_pre(bool integer) {
+  return integer ? (const void*)lof_stats_kernel<true, true> : (const void*)lof_stats_kernel<false, true>;
 }
 }  // namespace lofk

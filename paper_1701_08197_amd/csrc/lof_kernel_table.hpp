@@ -5,7 +5,9 @@
 
 namespace lofk {
 const void* kernel_stats(bool integer);
+const void* kernel_stats_pre(bool integer);         // statistics without pre-flagged samples
 const void* kernel_time(bool integer, int lanes);   // lanes: 32, 48 or 64
+const void* kernel_time_pre(bool integer, int lanes);   // starting from pre-flags
 const void* kernel_freq(bool integer);
 const void* kernel_sir_time(int lanes);
 const void* kernel_sir_freq();
@@ -13,4 +15,6 @@ const void* kernel_final(bool integer);
 const void* kernel_prose(bool freq);                // prose SIR reading: rows / columns
 const void* kernel_integrated(bool integer);        // integrated pre-correlation mode
 const void* kernel_post(bool integer);              // SIR + history + bytes, mask in LDS
+const void* kernel_partial_integrate(bool integer); // partial integration: tile means
+const void* kernel_partial_spread();                // partial integration: flag bytes
 }  // namespace lofk

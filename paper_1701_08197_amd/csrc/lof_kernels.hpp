@@ -134,7 +134,7 @@ __device__ __forceinline__ float fkey_inv(uint32_t k) {
 // Radix select of the order statistics r0 <= r1 over the block's keys
 // key(power) of KB bits (16: 12 + 4, 32: 12 + 12 + 8).  If have_pass0, hist[0]
 // already holds the first-digit histogram.
-template <bool INT, int KB, class SM, class KF>
+template <bool INT, int KB, bool PRE, class SM, class KF>
 __device__ __forceinline__ void radix_select_k(const DevBlock& b, SM& sm, uint32_t r0, uint32_t r1, bool have_pass0,
                                                KF key, uint32_t& k0, uint32_t& k1) {
   typedef typename PowT<INT>::T VT;
@@ -159,9 +159,10 @@ __device__ __forceinline__ void radix_select_k(const DevBlock& b, SM& sm, uint32
         const int t0 = (int)(it - (uint32_t)row * (uint32_t)nch) * 8;
         VT v[8];
         const int nv = load8<INT>(b, row, t0, v);
+        const uint32_t pm = pre8<PRE>(b, row, t0, nv);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-          if (j < nv) {
+          if (j < nv && !((pm >> j) & 1u)) {
             const uint32_t kv = key(v[j]);
             const uint32_t top = pass == 0 ? 0u : (kv >> hi);
             const uint32_t dg = (kv >> lo) & dmask;
@@ -186,11 +187,11 @@ __device__ __forceinline__ void radix_select_k(const DevBlock& b, SM& sm, uint32
   k1 = pre1;
 }
 
-template <bool INT, class SM>
+template <bool INT, bool PRE, class SM>
 __device__ __forceinline__ void radix_select(const DevBlock& b, SM& sm, uint32_t r0, uint32_t r1, bool have_pass0,
                                              uint32_t& k0, uint32_t& k1) {
   typedef typename PowT<INT>::T VT;
-  radix_select_k<INT, INT ? 16 : 32>(b, sm, r0, r1, have_pass0,
+  radix_select_k<INT, INT ? 16 : 32, PRE>(b, sm, r0, r1, have_pass0,
                                      [](VT v) { return INT ? (uint32_t)v : fkey((float)v); }, k0, k1);
 }
 
@@ -244,14 +245,17 @@ __device__ uint32_t find_dev_rank(const uint32_t* h, uint32_t med2, uint32_t ran
   return v;
 }
 
-template <bool INT, class SM>
+// PRE: the caller's pre-flagged samples (LOF_OPT_PREFLAGGED) leave every
+// statistic; N is then the number of the others (with none, median and stddev 0)
+template <bool INT, bool PRE, class SM>
 __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& P, SM& sm) {
   typedef typename PowT<INT>::T VT;
   const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
   const int nch = (b.T + 7) >> 3;
   const uint32_t items = (uint32_t)b.C * (uint32_t)nch;
   const FastDiv fd((uint32_t)nch);
-  const int64_t N = (int64_t)b.C * b.T;
+  int64_t N = (int64_t)b.C * b.T;
+  if (PRE && tid == 0) sm.nlive = 0u;
 
   if (INT) {
     for (int i = tid; i < IHIST_WORDS; i += WG) sm.u.ihist[i] = 0u;
@@ -263,10 +267,14 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
   unsigned long long s1u = 0, s2u = 0;
   double s1d = 0.0, s2d = 0.0;
   constexpr int U = 4;   // chunks of 8 samples in flight per thread
-  auto consume = [&](const VT (&v)[8], int nv) {
+  auto consume = [&](const VT (&v)[8], int nv, uint32_t pm) {
+    if (PRE) {
+      const int live = __popc(~pm & ((1u << nv) - 1u));
+      if (live) atomicAdd(&sm.nlive, (uint32_t)live);
+    }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      if (j < nv) {
+      if (j < nv && !((pm >> j) & 1u)) {
         if (INT) {
           // the exact histogram also yields sum(p) and sum(p^2) afterwards
           const uint32_t p = (uint32_t)v[j];
@@ -285,6 +293,7 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
     // count) so all U loads of a thread are in flight together
     for (uint32_t base = tid; base < items; base += (uint32_t)WG * U) {
       VT v[U][8];
+      uint32_t pm[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const uint32_t it = base + (uint32_t)u * WG;
@@ -292,9 +301,10 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
         const int row = (int)fd.div(ic);
         const int t0 = (int)(ic - (uint32_t)row * (uint32_t)nch) * 8;
         load8v<INT>(b, row, t0, v[u]);
+        pm[u] = pre8<PRE>(b, row, t0, 8);
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) consume(v[u], base + (uint32_t)u * WG < items ? 8 : 0);
+      for (int u = 0; u < U; ++u) consume(v[u], base + (uint32_t)u * WG < items ? 8 : 0, pm[u]);
     }
   } else {
     for (uint32_t it = tid; it < items; it += WG) {
@@ -302,10 +312,14 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
       const int t0 = (int)(it - (uint32_t)row * (uint32_t)nch) * 8;
       VT v[8];
       const int nv = load8<INT>(b, row, t0, v);
-      consume(v, nv);
+      consume(v, nv, pre8<PRE>(b, row, t0, nv));
     }
   }
-  const uint32_t r0 = (uint32_t)((N - 1) / 2), r1 = (uint32_t)(N / 2);
+  if (PRE) {
+    __syncthreads();
+    N = (int64_t)sm.nlive;
+  }
+  const uint32_t r0 = N > 0 ? (uint32_t)((N - 1) / 2) : 0u, r1 = (uint32_t)(N / 2);
   bool hist_ok = false;
   if (INT) {
     __syncthreads();   // every wave's histogram increments done
@@ -338,9 +352,10 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
         const int t0 = (int)(it - (uint32_t)row * (uint32_t)nch) * 8;
         VT v[8];
         const int nv = load8<INT>(b, row, t0, v);
+        const uint32_t pm = pre8<PRE>(b, row, t0, nv);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-          if (j < nv) {
+          if (j < nv && !((pm >> j) & 1u)) {
             const uint32_t p = (uint32_t)v[j];
             s1u += p;
             s2u += (unsigned long long)(p * p);     // p <= 32768: p*p <= 2^30
@@ -364,23 +379,25 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
   }
   __syncthreads();
 
-  uint32_t k0, k1;
-  if (INT && hist_ok) {
+  uint32_t k0 = 0, k1 = 0;
+  if (N == 0) {
+    // every sample pre-flagged: no statistics (median and stddev 0)
+  } else if (INT && hist_ok) {
     k0 = find_bin16(sm.u.ihist, r0, sm);
     k1 = (r1 == r0) ? k0 : find_bin16(sm.u.ihist, r1, sm);
   } else {
-    radix_select<INT>(b, sm, r0, r1, !INT, k0, k1);
+    radix_select<INT, PRE>(b, sm, r0, r1, !INT, k0, k1);
   }
   // robust stddev: the middle order statistics of the deviations from the median
   uint32_t m0 = 0, m1 = 0;
-  if (P.robust) {
+  if (P.robust && N > 0) {
     if (INT) {
       const uint32_t med2 = k0 + k1;   // twice the median (an integer)
       if (hist_ok) {
         m0 = find_dev_rank(sm.u.ihist, med2, r0, sm);
         m1 = (r1 == r0) ? m0 : find_dev_rank(sm.u.ihist, med2, r1, sm);
       } else {
-        radix_select_k<INT, 32>(b, sm, r0, r1, false, [med2](VT v) {
+        radix_select_k<INT, 32, PRE>(b, sm, r0, r1, false, [med2](VT v) {
           const int d = 2 * (int)(uint32_t)v - (int)med2;
           return (uint32_t)(d < 0 ? -d : d);
         }, m0, m1);
@@ -388,7 +405,7 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
     } else {
       const double v0 = (double)fkey_inv(k0), v1 = (double)fkey_inv(k1);
       const double med = (N & 1) ? v0 : (v0 + v1) / 2.0;
-      radix_select_k<INT, 32>(b, sm, r0, r1, false, [med](VT v) {
+      radix_select_k<INT, 32, PRE>(b, sm, r0, r1, false, [med](VT v) {
         return fkey((float)__builtin_fabs((double)v - med));
       }, m0, m1);
     }
@@ -404,7 +421,7 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
       S2d += sm.red_d[1][w];
     }
     double v0, v1;
-    if (INT) {
+    if (INT || N == 0) {
       v0 = (double)k0;
       v1 = (double)k1;
     } else {
@@ -422,9 +439,9 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
       ex2 = S2d / n;
     }
     double var = ex2 - mu * mu;
-    if (var < 0.0) var = 0.0;
+    if (var < 0.0 || N == 0) var = 0.0;
     double sd = __builtin_sqrt(var);
-    if (P.robust) {
+    if (P.robust && N > 0) {
       // 1.4826 * MAD; integer input: m0, m1 are doubled deviations
       double mad;
       if (INT) mad = ((double)m0 + (double)m1) / 4.0;
@@ -1055,6 +1072,95 @@ __device__ __forceinline__ void phase_time(const DevBlock& b, const DevParams& P
         } else {
           fm = st_core<INT, L>(ld, 0ull, lane, n, 0, nlev, sm);
         }
+        if (core) m0[(int64_t)row * W + (pos >> 6)] = fm;
+      }
+      if (INT && lane == 0) gp<uint64_t>(P.rowsum)[(int64_t)b.sidx * P.maxC + row] = rsum;
+    }
+  }
+}
+
+// ---- Phase B with caller-supplied pre-flags (LOF_OPT_PREFLAGGED)
+// pre-flag bits of a lane's nval <= L positions from time q of a row
+template <int L>
+__device__ __forceinline__ uint64_t pre_bits(const DevBlock& b, int row, int q, int nval) {
+  const GLB uint8_t* fb = gp<const uint8_t>(b.flags) + (int64_t)row * b.fstride + q;
+  uint64_t m = 0;
+  if (b.faligned && nval == L && (q & 15) == 0) {
+#pragma unroll
+    for (int j = 0; j < L / 16; ++j) {
+      const u32x4 w = *(const GLB u32x4*)(fb + 16 * j);
+      const uint32_t a[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int k = 0; k < 16; ++k) m |= ((a[k >> 2] >> (8 * (k & 3))) & 0xffu) ? (1ull << (16 * j + k)) : 0ull;
+    }
+  } else {
+    for (int i = 0; i < nval; ++i) m |= fb[i] ? (1ull << i) : 0ull;
+  }
+  return m;
+}
+
+// exact power sum of a lane's valid positions, pre-flagged ones included (the
+// history flagger subtracts the power of every flagged sample from the row sum)
+template <int L>
+__device__ __forceinline__ uint32_t lane_power_sum(TimeLoader<true, L>& ld) {
+  uint32_t D[L];
+  float Nc[L];
+  ld.fill(0ull, D, Nc);
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < L; ++i) s += D[i];
+  return (s - 4u * (uint32_t)(ld.ok ? ld.nval : 0)) >> 8;   // D = 256 p + 4: below 2^30
+}
+
+// SumThreshold along time from the pre-flags: each lane's positions start with
+// its pre-flag bits (pre-flagged samples leave the window sums and counts), the
+// windows built by doubling; integer rows also store their exact power sum
+template <bool INT, int L, class SM>
+__device__ __forceinline__ void phase_time_pre(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
+  const int T = b.T, C = b.C;
+  const int W = (T + 63) >> 6;
+  GLB uint64_t* m0 = gp<uint64_t>(P.maskw) + b.mask_off;
+  const int nlev = min(P.nl_t, ST_MAX_LEVELS);
+  if (T <= 64 * L) {
+    int G = 1;
+    while (G * L < T) G <<= 1;
+    const int R = 64 / G, lig = lane & (G - 1), grp = lane / G;
+    const int rb = chunk * NW * R + wv * R;
+    if (rb < C) {
+      const int row = rb + grp;
+      const bool ok = row < C;
+      const int q = lig * L, nval = clampi(T - q, 0, L);
+      TimeLoader<INT, L> ld{RowSrc(b), ok ? row : 0, q, nval, ok};
+      const uint64_t pre = ok ? pre_bits<L>(b, row, q, nval) : 0ull;
+      if constexpr (INT) {
+        uint32_t rs = lane_power_sum<L>(ld);
+        for (int d = G >> 1; d >= 1; d >>= 1) rs += __shfl_xor(rs, d, G);
+        if (ok && lig == 0) gp<uint64_t>(P.rowsum)[(int64_t)b.sidx * P.maxC + row] = rs;
+      }
+      const uint64_t fm = st_core<INT, L>(ld, pre, lig, T, 0, nlev, sm);
+      write_row_bits<L>(m0 + (int64_t)(ok ? row : 0) * W, W, fm, lig, G, ok);
+    }
+  } else if constexpr (L == 64) {
+    // long rows: segments of 64*L positions, SEG_CORE finished positions each
+    const int row = chunk * NW + wv;
+    if (row < C) {
+      uint64_t rsum = 0;
+      for (int c0 = 0; c0 < T; c0 += SEG_CORE) {
+        const int c1 = min(T, c0 + SEG_CORE);
+        const int q0 = max(0, c0 - SEG_HALO);
+        const int n = min(T, q0 + 64 * L) - q0;
+        const int pos = q0 + lane * L;
+        const int nvl = clampi(n - lane * L, 0, L);
+        TimeLoader<INT, L> ld{RowSrc(b), row, pos, nvl, true};
+        const uint64_t pre = pre_bits<L>(b, row, pos, nvl);
+        const bool core = pos >= c0 && pos < c1;
+        if constexpr (INT) {
+          uint32_t ps = core ? lane_power_sum<L>(ld) : 0u;
+          for (int d = 32; d >= 1; d >>= 1) ps += __shfl_xor(ps, d);   // < 2^27 per segment
+          rsum += ps;
+        }
+        const uint64_t fm = st_core<INT, L>(ld, pre, lane, n, 0, nlev, sm);
         if (core) m0[(int64_t)row * W + (pos >> 6)] = fm;
       }
       if (INT && lane == 0) gp<uint64_t>(P.rowsum)[(int64_t)b.sidx * P.maxC + row] = rsum;
@@ -2116,13 +2222,13 @@ __device__ __forceinline__ void run_items(int nitems, int* counter, F&& f) {
 
 // Phase A: power, median, stddev and thresholds of each block -> BlockState and
 // the caller's stats entry (whose flag totals the final kernel accumulates).
-template <bool INT>
+template <bool INT, bool PRE>
 __global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_stats_kernel(const DevBlock* __restrict__ blocks, int nb,
                                                                          int* counter, DevParams P) {
   __shared__ SmStats<INT> sm;
   run_items(nb, counter, [&](int bi) __attribute__((always_inline)) {
     const DevBlock b = blocks[bi];
-    phase_stats<INT>(b, P, sm);
+    phase_stats<INT, PRE>(b, P, sm);
     const int k = threadIdx.x;
     if (k < 18) {
       GLB BlockState* bs = gp<BlockState>(P.bstate) + b.sidx;
@@ -2151,6 +2257,20 @@ __global__ __launch_bounds__(WG, INT ? LOF_WAVES_PER_EU : float_waves_per_eu) vo
     if (ch >= time_chunks(b.C, b.T, L)) return;
     load_thresholds<INT>(b, P, sm);
     phase_time<INT, L>(b, P, sm, ch);
+  });
+}
+
+// Phase B, time direction, from caller-supplied pre-flags
+template <bool INT, int L>
+__global__ __launch_bounds__(WG, INT ? LOF_WAVES_PER_EU : float_waves_per_eu) void lof_time_pre_kernel(
+    const DevBlock* __restrict__ blocks, int nb, int maxch, int* counter, DevParams P) {
+  __shared__ SmThr sm;
+  run_items(nb * maxch, counter, [&](int it) __attribute__((always_inline)) {
+    const int bi = it / maxch, ch = it - bi * maxch;
+    const DevBlock b = blocks[bi];
+    if (ch >= time_chunks(b.C, b.T, L)) return;
+    load_thresholds<INT>(b, P, sm);
+    phase_time_pre<INT, L>(b, P, sm, ch);
   });
 }
 
