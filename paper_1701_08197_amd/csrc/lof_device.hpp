@@ -196,11 +196,11 @@ __device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? l
 __device__ __forceinline__ uint64_t ld_mask(const GLB uint64_t* p) { return *p; }
 
 // ---------------------------------------------------------------- power (Sec. 4)
-// complex int8 sample packed in 16 bits (re low byte, im high byte): exact power.
+// complex int8 sample packed in the low 16 bits of w16 (re low byte, im high
+// byte, upper bytes zero): exact power re^2 + im^2 as one 4-way int8 dot product
+// of the word with itself
 __device__ __forceinline__ uint32_t ci8_power(uint32_t w16) {
-  int re = (int)(int8_t)(w16 & 0xffu);
-  int im = (int)(int8_t)((w16 >> 8) & 0xffu);
-  return (uint32_t)(re * re + im * im);
+  return (uint32_t)__builtin_amdgcn_sdot4((int)w16, (int)w16, 0, false);
 }
 __device__ __forceinline__ float c64_power(float re, float im) { return re * re + im * im; }
 __device__ __forceinline__ float c64_amp(float re, float im) { return __builtin_sqrtf(re * re + im * im); }

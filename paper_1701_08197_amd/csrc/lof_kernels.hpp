@@ -1977,11 +1977,15 @@ __device__ __forceinline__ void row_unflagged(const DevBlock& b, MP mrow, int ro
         for (int j = 0; j < 8; ++j) {
           const u32x4 q = *(const GLB u32x4*)(rb + 16 * j);
           const uint32_t a4[4] = {q.x, q.y, q.z, q.w};
+          const int f8 = (int)(uint32_t)(fw >> (8 * j));
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
-            const uint32_t f = (uint32_t)(fw >> (8 * j + 2 * m));
-            sf += (f & 1u) ? ci8_power(a4[m] & 0xffffu) : 0u;
-            sf += (f & 2u) ? ci8_power(a4[m] >> 16) : 0u;
+            // the word's two samples kept by their flag bits (sign-extended bit
+            // fields), then re^2 + im^2 of the kept ones in one int8 dot product
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_sbfe(f8, 2 * m, 1);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_sbfe(f8, 2 * m + 1, 1);
+            const uint32_t keep = (lo & 0xffffu) | (hi & 0xffff0000u);
+            sf = (uint32_t)__builtin_amdgcn_sdot4((int)(a4[m] & keep), (int)a4[m], (int)sf, false);
           }
         }
       } else {
@@ -2190,6 +2194,11 @@ __device__ __forceinline__ void phase_write(const DevBlock& b, const DevParams& 
 // the packed integer form): 2 waves per SIMD, 256 VGPRs, no spills.  The float
 // frequency slab (81 KB of LDS) allows one workgroup per CU anyway.
 constexpr int float_waves_per_eu = 2;
+// The history-and-bytes kernel is a chain of dependent global loads per row
+// (ring and row sum, mask words, flagged samples): 8 waves per SIMD hide them.
+#ifndef LOF_FINAL_WAVES_PER_EU
+#define LOF_FINAL_WAVES_PER_EU 8
+#endif
 // SIR along time moves little data per work item and waits on dependent global
 // loads: more resident waves (6 per SIMD) pay more than the few spills they cost.
 #ifndef LOF_SIRT_WAVES_PER_EU
@@ -2303,7 +2312,7 @@ __global__ __launch_bounds__(WG, LOF_SIRT_WAVES_PER_EU) void lof_sir_time_kernel
 
 // Phase D: history flagger and flag bytes, rows in chunks of NW
 template <bool INT>
-__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_final_kernel(const DevBlock* __restrict__ blocks, int nb,
+__global__ __launch_bounds__(WG, LOF_FINAL_WAVES_PER_EU) void lof_final_kernel(const DevBlock* __restrict__ blocks, int nb,
                                                                          int maxch, int* counter, DevParams P) {
   __shared__ SmFinal sm;
   run_items(nb * maxch, counter, [&](int it) __attribute__((always_inline)) {
