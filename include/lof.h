@@ -192,12 +192,17 @@ typedef struct {
  * lane holds (32, 48 or 64; a row must fit 64 lanes unless the value is 64).
  * persistent = 1 launches each phase kernel as a chip-sized grid whose
  * workgroups take (block, chunk) items from a work counter (largest block
- * first) instead of one workgroup per item. */
+ * first) instead of one workgroup per item.  fuse_post selects, for blocks of
+ * at most 64 channels and 4096 times, the one-kernel-per-block pass that runs
+ * SIR, the history flagger and the flag bytes with the block's mask in LDS:
+ * 0 = when a call holds at least as many such blocks of a kind as the GPU has
+ * compute units (fewer blocks spread better over row and column chunks),
+ * 1 = always, 2 = never. */
 #define LOF_TUNE_BUCKETS 5
 typedef struct {
   int32_t time_lanes[2][LOF_TUNE_BUCKETS];
   int32_t persistent;
-  int32_t _reserved;
+  int32_t fuse_post;
 } lof_tuning;
 
 typedef struct {

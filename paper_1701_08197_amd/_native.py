@@ -86,7 +86,7 @@ class LofTuning(ctypes.Structure):
     _fields_ = [
         ("time_lanes", (ctypes.c_int32 * LOF_TUNE_BUCKETS) * 2),
         ("persistent", ctypes.c_int32),
-        ("_reserved", ctypes.c_int32),
+        ("fuse_post", ctypes.c_int32),
     ]
 
 

@@ -342,7 +342,7 @@ void default_tuning(lof_tuning* t) {
 }
 
 bool tuning_ok(const lof_tuning* t) {
-  if (!t || (t->persistent != 0 && t->persistent != 1)) return false;
+  if (!t || (t->persistent != 0 && t->persistent != 1) || t->fuse_post < 0 || t->fuse_post > 2) return false;
   for (int k = 0; k < 2; ++k)
     for (int b = 0; b < LOF_TUNE_BUCKETS; ++b)
       if (!lanes_allowed(t->time_lanes[k][b], b)) return false;
@@ -522,8 +522,9 @@ void enqueue(lof_ctx* c, const lof_tuning& t, Slot& s, const int* counts, int n,
     const int mf = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::freq_chunks(integer, b.C, b.T); });
     launch(c, t, K_FREQ + kind, LOF_PHASE_ST_FREQ, dk, kcnt, mf, s, nc, st, P);
     // blocks of at most 64 channels and 4096 times: SIR, history and flag bytes in
-    // one kernel per block with the mask in LDS
-    bool post = !P.prose;
+    // one kernel per block with the mask in LDS, when the blocks fill the chip
+    // (fewer blocks than CUs: the row- and column-chunked kernels spread them)
+    bool post = !P.prose && (t.fuse_post == 1 || (t.fuse_post == 0 && kcnt >= c->n_cu));
     for (int i = 0; post && i < kcnt; ++i) post = lofk::post_eligible(hk[i].C, hk[i].T);
     if (post) {
       launch(c, t, K_POST + kind, LOF_PHASE_FINAL, dk, kcnt, 1, s, nc, st, P);

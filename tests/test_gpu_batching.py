@@ -63,6 +63,7 @@ def all_tunings():
                     allowed = [32, 48, 64] if b < 2 else ([48, 64] if b == 2 else [64])
                     t.time_lanes[k][b] = lanes if lanes in allowed else 64
             t.persistent = pers
+            t.fuse_post = (lanes + pers) % 3      # the fused SIR/history pass: auto, always, never
             out.append(t)
     return out
 

@@ -15,12 +15,18 @@ from tests.gpu_util import mismatch, oracle_params, run_gpu, say
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def lof():
+@pytest.fixture(scope="module", params=[1, 2], ids=["fused_post", "chunked_post"])
+def lof(request):
+    """Blocks of at most 64 channels and 4096 times take either the one-kernel
+    SIR/history/bytes pass (fuse_post = 1) or the row- and column-chunked kernels
+    (fuse_post = 2): every test runs on both."""
     import torch  # noqa: F401
     import paper_1701_08197_amd as P
     fl = P.Flagger(P.default_params(max_streams=64, max_channels=1024, max_blocks_per_call=64,
                                     max_samples_per_call=1 << 24))
+    t = fl.get_tuning()
+    t.fuse_post = request.param
+    fl.set_tuning(t)
     yield fl
     fl.close()
 
