@@ -22,6 +22,7 @@ the input is integer), favouring obviousness over speed:
 * robust stddev from the MAD .................. Sec. 4.2 (statistics list)
 * 2-D flagging with partial integration ....... Sec. 4 (integration paragraph, the
                                                  alternative method)
+* winsorized history statistics ............... Sec. 4.2 (statistics list)
 * caller-supplied pre-flags ................... Sec. 4.2 (statistics of the unflagged
                                                  samples), Sec. 2.1 (flagged samples
                                                  leave the window sums)
@@ -65,6 +66,7 @@ class Params:
     literal_history_tie: bool = False  # True: flag when cur >= thr (listing's else-branch)
     sir_prose: bool = False            # True: the prose reading of Sec. 2.2 (sir_prose_rows)
     robust_sigma: bool = False         # True: stddev from the MAD (block_mad_sigma, Sec. 4.2)
+    history_winsor: int = 0            # k > 0: the ring's mean and stddev after winsorizing k per side
 
     @property
     def levels_freq(self) -> int:
@@ -311,12 +313,25 @@ class History:
                 del r[0]
 
 
+def winsorize_ring(ring: list, k: int) -> list:
+    """Winsorized history (Sec. 4.2 lists winsorized means among the statistics):
+    the k smallest committed means are replaced by the (k+1)-th smallest and the
+    k largest by the (k+1)-th largest (k at most (L-1)//2 for L values), in ring
+    order."""
+    L = len(ring)
+    k = min(k, (L - 1) // 2)
+    srt = sorted(ring)
+    lo, hi = srt[k], srt[L - 1 - k]
+    return [min(max(x, lo), hi) for x in ring]
+
+
 def history_row(cur_sum, n_unflagged: int, ring: list, params: Params):
     """Compare one channel's current mean with its history (Sec. 4.1 listing).
 
     Returns (flag, pending) where pending is None when nothing is pushed.
     cur = mean of unflagged samples; with at least history_min committed means,
-    thr = mean(ring) + history_sensitivity * std(ring) (population, sequential sums);
+    thr = mean(ring) + history_sensitivity * std(ring) (population, sequential sums;
+    with history_winsor = k, of the winsorized ring, winsorize_ring);
     the channel is flagged when cur > thr (or >= with the literal tie) and then the
     pushed value is thr, else cur.  During warm-up the value is pushed unflagged; a
     fully flagged channel neither flags nor pushes."""
@@ -326,6 +341,8 @@ def history_row(cur_sum, n_unflagged: int, ring: list, params: Params):
     L = len(ring)
     if L < params.history_min:
         return False, float(cur)
+    if params.history_winsor > 0:
+        ring = winsorize_ring(ring, params.history_winsor)
     acc = 0.0
     for x in ring:
         acc += x

@@ -854,3 +854,44 @@ def test_preflags_tiny_exhaustive_vs_rational_bruteforce(seed):
     mt = run([[int(v) for v in row] for row in p], pre.tolist())
     mf = run([[int(v) for v in col] for col in p.T], mt.T.tolist()).T
     assert (r.st_mask == mf).all()
+
+
+# ------------------------------------------------------ winsorized history statistics
+def test_winsorize_ring_hand_worked():
+    assert O.winsorize_ring([1.0, 2.0, 3.0, 4.0, 100.0], 1) == [2.0, 2.0, 3.0, 4.0, 4.0]
+    assert O.winsorize_ring([5.0, -7.0, 5.0, 9.0], 1) == [5.0, 5.0, 5.0, 5.0]   # k = 1: 2nd smallest, 2nd largest
+    assert O.winsorize_ring([3.0, 1.0], 5) == [3.0, 1.0]                      # k capped at (L-1)//2 = 0
+
+
+@pytest.mark.parametrize("L,k", [(5, 1), (8, 2), (32, 3), (33, 16), (7, 0)])
+def test_winsorize_ring_equals_scipy(L, k):
+    from scipy.stats import mstats
+    rng = np.random.default_rng(L * 10 + k)
+    ring = rng.standard_normal(L).tolist()
+    ring[3 % L] = 50.0
+    want = np.asarray(mstats.winsorize(np.array(ring), limits=((k + 0.5) / L, (k + 0.5) / L))).tolist()
+    assert O.winsorize_ring(ring, k) == want
+
+
+def test_winsorized_history_threshold_closed_form():
+    # ring [1, 2, 3, 4, 100], k = 1 -> [2, 2, 3, 4, 4]: mean 3, variance 0.8
+    # (threshold 3 + 2 sqrt(0.8) = 4.79: a current mean of 10 is flagged and the
+    # threshold is pushed)
+    prm = O.Params(history_min=1, history_winsor=1, history_sensitivity=2.0)
+    f, pv = O.history_row(100, 10, [1.0, 2.0, 3.0, 4.0, 100.0], prm)
+    thr = 3.0 + 2.0 * np.sqrt(0.8)
+    assert f and pv == pytest.approx(thr, rel=1e-15)
+    # without winsorizing the outlier inflates the threshold (mean 22, stddev 39)
+    # far above the current mean
+    f0, pv0 = O.history_row(100, 10, [1.0, 2.0, 3.0, 4.0, 100.0], O.Params(history_min=1, history_sensitivity=2.0))
+    assert not f0 and pv0 == 10.0
+
+
+def test_winsorized_history_ignores_an_outlier_second():
+    # one second of strong broadband RFI committed into the ring does not move the
+    # winsorized threshold, whatever its size
+    prm = O.Params(history_min=1, history_winsor=1)
+    base = [10.0, 10.5, 9.5, 10.2, 9.8, 10.1]
+    t1 = O.history_row(0, 1, base + [1e3], prm)
+    t2 = O.history_row(0, 1, base + [1e9], prm)
+    assert t1 == t2
