@@ -168,7 +168,12 @@ typedef struct {
                                   rows of tiles.  Not with LOF_OPT_INTEGRATED or
                                   LOF_OPT_GRAPH, nor in lof_autotune or
                                   lof_flag_blocks_static (LOF_ERR_INVALID).        */
-  int32_t _reserved1;
+  int32_t history_winsor;      /* k > 0: the history flagger takes the mean and stddev
+                                  of its committed means after winsorizing them (Sec. 4.2
+                                  lists winsorized means): the k smallest become the
+                                  (k+1)-th smallest and the k largest the (k+1)-th
+                                  largest (k at most (L-1)/2 for L committed values);
+                                  0 = plain statistics.  Needs history_len <= 64.   */
 } lof_params;
 
 typedef struct {

@@ -54,7 +54,7 @@ class LofParams(ctypes.Structure):
         ("options", ctypes.c_uint32),
         ("partial_time", ctypes.c_int32),
         ("partial_freq", ctypes.c_int32),
-        ("_reserved1", ctypes.c_int32),
+        ("history_winsor", ctypes.c_int32),
     ]
 
 

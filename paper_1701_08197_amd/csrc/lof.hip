@@ -106,6 +106,7 @@ constexpr int NCOUNTER = 32;      // persistent-launch work counters per call (<
 constexpr int NTEV = NCOUNTER + 1;   // phase-timing events per call
 
 struct Slot {
+  int ncx = 0;                    // blocks of complex float input at the head of the 32-lane float group
   DevBlock* d_desc = nullptr;
   DevBlock* h_desc = nullptr;     // pinned
   uint64_t* d_mask = nullptr;
@@ -147,7 +148,7 @@ constexpr int NVAR = 6;   // time layouts: (integer, float) x (32, 48, 64 lanes)
 // kernels, for occupancy lookups
 enum KernId {
   K_STATS = 0, K_TIME = 2, K_FREQ = 8, K_SIRT = 10, K_SIRF = 13, K_FINAL = 14, K_PROSE = 16, K_INTEG = 18, K_POST = 20,
-  K_STATS_PRE = 22, K_TIME_PRE = 24, NKERN = 30
+  K_STATS_PRE = 22, K_TIME_PRE = 24, K_TIMECX = 30, NKERN = 31
 };
 int variant_lanes(int v) { return v % 3 == 0 ? 32 : (v % 3 == 1 ? 48 : 64); }
 
@@ -224,6 +225,8 @@ DevParams dev_params(const lof_ctx* c, uint64_t* mask, uint64_t* mask2, BlockSta
   P.integrated = (c->prm.options & LOF_OPT_INTEGRATED) ? 1 : 0;
   P.integ_tmax = 0;
   P.robust = (c->prm.options & LOF_OPT_ROBUST_SIGMA) ? 1 : 0;
+  P.winsor = c->prm.history_winsor;
+  P._pad = 0;
   P.ring = c->ring;
   P.rcount = c->rcount;
   P.rhead = c->rhead;
@@ -248,6 +251,8 @@ const char* check_params(const lof_params* p) {
     return "SIR eta must be num/den with 0 <= num <= den <= 1024";
   if (p->history_len < 1 || p->history_len > 4096) return "history_len must be in 1..4096";
   if (p->history_min < 0) return "history_min must be >= 0";
+  if (p->history_winsor < 0 || (p->history_winsor > 0 && p->history_len > 64))
+    return "history_winsor must be >= 0, and 0 unless history_len <= 64";
   if (p->max_streams < 1) return "max_streams must be >= 1";
   if (p->max_channels < 1 || p->max_channels > LOF_MAX_CHANNELS) return "max_channels must be in 1..1024";
   if (p->max_blocks_per_call < 1) return "max_blocks_per_call must be >= 1";
@@ -285,6 +290,7 @@ const void* kernel_of(int k) {
   if (k == K_STATS_PRE || k == K_STATS_PRE + 1) return lofk::kernel_stats_pre(k == K_STATS_PRE);
   if (k >= K_TIME_PRE && k < K_TIME_PRE + 6)
     return lofk::kernel_time_pre(k < K_TIME_PRE + 3, variant_lanes(k - K_TIME_PRE));
+  if (k == K_TIMECX) return lofk::kernel_time_cx();
   return lofk::kernel_final(k == K_FINAL);
 }
 
@@ -414,9 +420,13 @@ lof_status validate(lof_ctx* c, const lof_block* blocks, int32_t n, bool check_i
 void build_table(int* order, const lof_tuning& t, const lof_block* blocks, int32_t n, Slot& s, int* counts,
                  bool history) {
   for (int i = 0; i < n; ++i) order[i] = i;
+  // within a variant, float blocks of complex input first (their 32-lane time
+  // kernel keeps the formed powers), then by decreasing size
+  auto cx = [&](const lof_block& b) { return b.dtype == LOF_C64 || b.dtype == LOF_C64_AMP; };
   std::sort(order, order + n, [&](int a, int bb) {
     const int va = variant_of(t, blocks[a]), vb = variant_of(t, blocks[bb]);
     if (va != vb) return va < vb;
+    if (cx(blocks[a]) != cx(blocks[bb])) return cx(blocks[a]);
     const int64_t sa = (int64_t)blocks[a].n_channels * blocks[a].n_times;
     const int64_t sb = (int64_t)blocks[bb].n_channels * blocks[bb].n_times;
     if (sa != sb) return sa > sb;
@@ -445,6 +455,9 @@ void build_table(int* order, const lof_tuning& t, const lof_block* blocks, int32
     moff += (int64_t)b.n_channels * ((b.n_times + 63) / 64);
     counts[variant_of(t, b)]++;
   }
+  s.ncx = 0;
+  for (int j = 0; j < n; ++j)
+    if (variant_of(t, blocks[order[j]]) == 3 && cx(blocks[order[j]])) s.ncx++;
 }
 
 // one kernel launch over nb blocks (maxch > 0: chunked kernel, nb * maxch items)
@@ -516,8 +529,18 @@ void enqueue(lof_ctx* c, const lof_tuning& t, Slot& s, const int* counts, int n,
       if (!cnt) continue;
       const int L = variant_lanes(j);
       mt[j] = max_chunks(hk + voff, cnt, [&](const DevBlock& b) { return lofk::time_chunks(b.C, b.T, L); });
-      launch(c, t, (pre ? K_TIME_PRE : K_TIME) + 3 * kind + j, LOF_PHASE_ST_TIME, dk + voff, cnt, mt[j], s, nc, st,
-             P);
+      // float rows of complex input at 32 lanes (the group's head) keep their powers
+      const int ncx = (!pre && kind == 1 && j == 0) ? s.ncx : 0;
+      if (ncx > 0) {
+        const int mx = max_chunks(hk + voff, ncx, [&](const DevBlock& b) { return lofk::time_chunks(b.C, b.T, L); });
+        launch(c, t, K_TIMECX, LOF_PHASE_ST_TIME, dk + voff, ncx, mx, s, nc, st, P);
+      }
+      if (cnt > ncx) {
+        const int mr = max_chunks(hk + voff + ncx, cnt - ncx,
+                                  [&](const DevBlock& b) { return lofk::time_chunks(b.C, b.T, L); });
+        launch(c, t, (pre ? K_TIME_PRE : K_TIME) + 3 * kind + j, LOF_PHASE_ST_TIME, dk + voff + ncx, cnt - ncx, mr, s,
+               nc, st, P);
+      }
     }
     const int mf = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::freq_chunks(integer, b.C, b.T); });
     launch(c, t, K_FREQ + kind, LOF_PHASE_ST_FREQ, dk, kcnt, mf, s, nc, st, P);

@@ -132,6 +132,8 @@ struct DevParams {
   int32_t integrated;    // integrated pre-correlation mode
   int32_t integ_tmax;    // longest block of the call (integrated mode: LDS layout)
   int32_t robust;        // stddev from the MAD
+  int32_t winsor;        // history: committed means winsorized k per side (0: off)
+  int32_t _pad;
   double* ring;          // [streams][maxC][H]
   int32_t* rcount;       // [streams][maxC]
   int32_t* rhead;        // [streams][maxC]

@@ -444,7 +444,27 @@ __device__ __forceinline__ void integ_flag_series(const IntegSm& s, const uint64
       int64_t Si = 0;
       double Sf = 0.0;
       int cnt = 0;
-      for (int j = a; j < a + I; ++j) {
+      // the first window, 8 positions at a time so their LDS reads are in flight
+      // together (the sum is still taken in position order)
+      int j = a;
+      for (; j + 8 <= a + I; j += 8) {
+        uint64_t v[8];
+        bool fl[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          fl[q] = (s.mask[(j + q) >> 6] >> ((j + q) & 63)) & 1ull;
+          v[q] = vals[j + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          if (!fl[q]) {
+            ++cnt;
+            if (INT) Si += (int64_t)v[q];
+            else Sf += __longlong_as_double((long long)v[q]);
+          }
+        }
+      }
+      for (; j < a + I; ++j) {
         const bool fl = (s.mask[j >> 6] >> (j & 63)) & 1ull;
         if (!fl) {
           ++cnt;

@@ -955,6 +955,29 @@ struct TimeLoader {
   }
 };
 
+// float rows of complex input: the lane's powers (or amplitudes) formed once and
+// kept, so a level that changed the mask rebuilds its window sums from registers
+// instead of reloading the row and forming them again
+template <int L>
+struct CachedRow {
+  float V[L];
+  int nval;
+  bool ok;
+  template <class LD>
+  __device__ __forceinline__ explicit CachedRow(LD& ld) : nval(ld.nval), ok(ld.ok) {
+    float Nc[L];
+    ld.fill(0ull, V, Nc);
+  }
+  __device__ __forceinline__ void fill(uint64_t fm, float (&D)[L], float (&Nc)[L]) {
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const bool live = ok && i < nval && !((fm >> i) & 1ull);
+      D[i] = live ? V[i] : 0.0f;
+      Nc[i] = live ? 1.0f : 0.0f;
+    }
+  }
+};
+
 // frequency loader: one column of the LDS slab (rows = channels)
 template <bool INT, int L>
 struct TileLoader {
@@ -1017,7 +1040,8 @@ __device__ __forceinline__ void or_bit_lds(uint64_t* w, int idx, int bit) {
 }
 
 // ===================================================================== phase B
-template <bool INT, int L, class SM>
+// CX: float rows of complex input, the formed powers kept in registers
+template <bool INT, int L, bool CX, class SM>
 __device__ __forceinline__ void phase_time(const DevBlock& b, const DevParams& P, SM& sm, const int chunk) {
   const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
   const int T = b.T, C = b.C;
@@ -1040,6 +1064,10 @@ __device__ __forceinline__ void phase_time(const DevBlock& b, const DevParams& P
         uint32_t psum;
         fm = st_core_px<L>(ld, lig, G, T, nlev, sm, psum,
                            gp<uint64_t>(P.rowsum) + (int64_t)b.sidx * P.maxC + (ok ? row : 0));
+      } else if constexpr (CX) {
+        // complex input: the powers (or amplitudes) are formed once per lane
+        CachedRow<L> cr(ld);
+        fm = st_core<INT, L>(cr, 0ull, lig, T, 0, nlev, sm);
       } else {
         fm = st_core<INT, L>(ld, 0ull, lig, T, 0, nlev, sm);
       }
@@ -2059,9 +2087,25 @@ __device__ __forceinline__ void history_judge(const DevParams& P, int64_t idx, i
   bool flag = false;
   double pushv = cur;
   if (judge) {
+    // winsorized history (rings of at most 64): the values of rank k and L-1-k
+    // (ties by ring order) bound every committed mean
+    double xw = x0;
+    if (P.winsor > 0 && L > 0) {
+      const int k = min(P.winsor, (L - 1) / 2);
+      int rank = 0;
+      for (int q = 0; q < L; ++q) {
+        const double y = lane_double(x0, q);
+        rank += (y < x0 || (y == x0 && q < lane)) ? 1 : 0;
+      }
+      const uint64_t blo = __ballot(lane < L && rank == k);
+      const uint64_t bhi = __ballot(lane < L && rank == L - 1 - k);
+      const double lo = lane_double(x0, __ffsll((unsigned long long)blo) - 1);
+      const double hi = lane_double(x0, __ffsll((unsigned long long)bhi) - 1);
+      if (lane < L) xw = x0 < lo ? lo : (x0 > hi ? hi : x0);
+    }
     double acc = 0.0;
     for (int j0 = 0; j0 < L; j0 += 64) {
-      double x = x0;
+      double x = xw;
       if (j0 > 0) {
         int k = head - L + j0 + lane;
         if (k < 0) k += P.H;
@@ -2073,7 +2117,7 @@ __device__ __forceinline__ void history_judge(const DevParams& P, int64_t idx, i
     const double hm = acc / (double)L;
     acc = 0.0;
     for (int j0 = 0; j0 < L; j0 += 64) {
-      double x = x0;
+      double x = xw;
       if (j0 > 0) {
         int k = head - L + j0 + lane;
         if (k < 0) k += P.H;
@@ -2255,8 +2299,9 @@ __global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_stats_kernel(const D
   });
 }
 
-// Phase B, time direction: rows of a block in chunks
-template <bool INT, int L>
+// Phase B, time direction: rows of a block in chunks (CX: float rows of complex
+// input with the formed powers kept, 32 samples per lane)
+template <bool INT, int L, bool CX = false>
 __global__ __launch_bounds__(WG, INT ? LOF_WAVES_PER_EU : float_waves_per_eu) void lof_time_kernel(const DevBlock* __restrict__ blocks, int nb,
                                                                         int maxch, int* counter, DevParams P) {
   __shared__ SmThr sm;
@@ -2265,7 +2310,7 @@ __global__ __launch_bounds__(WG, INT ? LOF_WAVES_PER_EU : float_waves_per_eu) vo
     const DevBlock b = blocks[bi];
     if (ch >= time_chunks(b.C, b.T, L)) return;
     load_thresholds<INT>(b, P, sm);
-    phase_time<INT, L>(b, P, sm, ch);
+    phase_time<INT, L, CX>(b, P, sm, ch);
   });
 }
 

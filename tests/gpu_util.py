@@ -29,7 +29,8 @@ def oracle_params(fp) -> O.Params:
                     history_min=fp.history_min,
                     literal_history_tie=bool(fp.options & 0x2),
                     sir_prose=bool(fp.options & 0x10),
-                    robust_sigma=bool(fp.options & 0x40))
+                    robust_sigma=bool(fp.options & 0x40),
+                    history_winsor=fp.history_winsor)
 
 
 def run_gpu(flagger, items, stream=None):

@@ -32,11 +32,13 @@ def history_case(seed, steps, C, T, n_streams, level_jump_step=None):
     return blocks
 
 
-@pytest.mark.parametrize("literal", [False, True])
-def test_history_sequence_exact(literal):
-    say(f"[history_sequence_exact] literal={literal}")
+@pytest.mark.parametrize("literal,winsor", [(False, 0), (True, 0), (False, 2)])
+def test_history_sequence_exact(literal, winsor):
+    """Flags, staged values and rings over 10 steps; with winsor = 2 the ring's
+    statistics are those of the winsorized ring (k = 1 or 2 as it fills)."""
+    say(f"[history_sequence_exact] literal={literal} winsor={winsor}")
     opts = 0x2 if literal else 0
-    fl = make(history_len=6, history_min=3, history_sensitivity=2.0, options=opts)
+    fl = make(history_len=6, history_min=3, history_sensitivity=2.0, options=opts, history_winsor=winsor)
     prm = oracle_params(fl.params)
     h = O.History(prm)
     steps, C, T, ns = 10, 24, 500, 3
