@@ -880,8 +880,8 @@ def main():
     ap.add_argument("--serve-wall", type=float, default=3.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the blocks are independent and "
-              f"shard by stream across GPUs, but multi-GPU runs are not part of this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for {args.gpus}): the blocks are independent and would shard "
+              f"by stream across GPUs with no exchange, but only the one-GPU path is implemented.", file=sys.stderr)
         sys.exit(2)
     cores = min(len(os.sched_getaffinity(0)), 16)
     workers = args.workers or cores

@@ -1899,6 +1899,10 @@ __device__ __forceinline__ void phase_prose_freq(const DevBlock& b, const DevPar
 }
 
 // flag bytes of one row word: nv (<= 64) samples from t0, bit j -> byte j
+// four flag bits -> four 0/1 bytes: bit k of nib times 2^(7k) lands at bit 8k
+// (the shifted copies of a 4-bit value do not overlap, so nothing carries)
+__device__ __forceinline__ uint32_t nibble_bytes(uint32_t nib) { return (nib * 0x00204081u) & 0x01010101u; }
+
 __device__ __forceinline__ void write_word_bytes(const DevBlock& b, int row, int t0, int nv, uint64_t w) {
   GLB uint8_t* fp = gp<uint8_t>(b.flags) + (int64_t)row * b.fstride + t0;
   if (b.faligned && nv == 64) {
@@ -1909,7 +1913,7 @@ __device__ __forceinline__ void write_word_bytes(const DevBlock& b, int row, int
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const uint32_t nib = (h >> (4 * j)) & 0xfu;
-        o[j] = (nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21);
+        o[j] = nibble_bytes(nib);
       }
       *(GLB u32x4*)(fp + 16 * q) = u32x4{o[0], o[1], o[2], o[3]};
     }
@@ -2209,7 +2213,7 @@ __device__ __forceinline__ void phase_write(const DevBlock& b, const DevParams& 
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const uint32_t nib = (fb >> (4 * j)) & 0xfu;
-        o[j] = (nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21);
+        o[j] = nibble_bytes(nib);
       }
       *(GLB u32x4*)fp = u32x4{o[0], o[1], o[2], o[3]};
     } else {

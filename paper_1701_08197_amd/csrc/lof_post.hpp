@@ -111,18 +111,35 @@ __device__ __forceinline__ void phase_post(const DevBlock& b, const DevParams& P
   // history flagger per row (one wave per row), then the flag bytes
   const int s = b.stream_id;
   if (s >= 0) {
-    for (int row = wv; row < C; row += NW) {
+    // a wave's rows in turn; the next row's ring count, head, ring and row sum
+    // are loaded while the current row is judged
+    const bool small_ring = P.H <= 64;
+    auto fetch = [&](int row, int& L, int& head, double& xs, uint64_t& rs) {
       const int64_t idx = (int64_t)s * P.maxC + row;
-      const int L = gp<const int32_t>(P.rcount)[idx];
-      const int head = gp<const int32_t>(P.rhead)[idx];
+      L = gp<const int32_t>(P.rcount)[idx];
+      head = gp<const int32_t>(P.rhead)[idx];
+      xs = (small_ring && lane < P.H) ? gp<const double>(P.ring)[idx * P.H + lane] : 0.0;
+      rs = INT ? gp<const uint64_t>(P.rowsum)[(int64_t)b.sidx * P.maxC + row] : 0ull;
+    };
+    int L = 0, head = 0;
+    double xs = 0.0;
+    uint64_t rowsum = 0;
+    if (wv < C) fetch(wv, L, head, xs, rowsum);
+    for (int row = wv; row < C; row += NW) {
+      int L2 = 0, head2 = 0;
+      double xs2 = 0.0;
+      uint64_t rs2 = 0;
+      if (row + NW < C) fetch(row + NW, L2, head2, xs2, rs2);
+      const int64_t idx = (int64_t)s * P.maxC + row;
       const GLB double* ring = gp<const double>(P.ring) + idx * P.H;
-      const bool small_ring = P.H <= 64;
-      const double xs = (small_ring && lane < P.H) ? ring[lane] : 0.0;
-      const uint64_t rowsum = INT ? gp<const uint64_t>(P.rowsum)[(int64_t)b.sidx * P.maxC + row] : 0ull;
       double usum;
       int cnt;
       row_unflagged<INT>(b, (const uint64_t*)(sm.w + row * W), row, lane, rowsum, usum, cnt);
       history_judge(P, idx, L, head, ring, xs, small_ring, usum, cnt, lane, sm.rowflag, row);
+      L = L2;
+      head = head2;
+      xs = xs2;
+      rowsum = rs2;
     }
     __syncthreads();
   }
