@@ -56,7 +56,7 @@ DEADLINE_S = synth.CFG1_SECOND_S          # 3072 samples of 327.68 us
 # kernel of each phase for the default workload (complex int8, 48 samples per lane)
 # (blocks of at most 64 channels and 4096 times: SIR, history and flag bytes run
 # in one kernel, timed as the history_write phase)
-PHASE_KERNEL = {"stats": "lof_stats_kernel<true>", "sumthreshold_time": "lof_time_kernel<true, 48>",
+PHASE_KERNEL = {"stats": "lof_stats_kernel<true, false>", "sumthreshold_time": "lof_time_kernel<true, 48, false>",
                 "sumthreshold_freq": "lof_freq_kernel<true>", "sir_time": "lof_sir_time_kernel<48>",
                 "sir_freq": "lof_sir_freq_kernel", "history_write": "lof_post_kernel<true>"}
 # bytes each phase must move per sample in the default workload given the phase
