@@ -266,7 +266,7 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
 
   unsigned long long s1u = 0, s2u = 0;
   double s1d = 0.0, s2d = 0.0;
-  constexpr int U = 4;   // chunks of 8 samples in flight per thread
+  constexpr int U = 8;   // chunks of 8 samples in flight per thread
   auto consume = [&](const VT (&v)[8], int nv, uint32_t pm) {
     if (PRE) {
       const int live = __popc(~pm & ((1u << nv) - 1u));
