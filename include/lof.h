@@ -267,10 +267,12 @@ lof_status lof_get_tuning(const lof_ctx* ctx, lof_tuning* out);
 lof_status lof_set_tuning(lof_ctx* ctx, const lof_tuning* tuning);
 
 /* Autotuner: times every allowed time_lanes value for each (kind, bucket) that
- * occurs in `blocks`, and the two launch modes, on these blocks, and keeps the
- * fastest in ctx (synchronous; `reps` timed launches per candidate).  It writes
- * the blocks' flag outputs but stages no history (tuning runs ignore stream
- * ids).  *out (host, nullable) receives the chosen tuning. */
+ * occurs in `blocks`, the two launch modes, and (for blocks of at most 64
+ * channels and 4096 times) the fused or chunked SIR/history pass, on these
+ * blocks, and keeps the fastest in ctx (synchronous; `reps` timed launches
+ * per candidate).  It writes the blocks' flag outputs but stages no history
+ * (tuning runs ignore stream ids).  *out (host, nullable) receives the chosen
+ * tuning. */
 lof_status lof_autotune(lof_ctx* ctx, const lof_block* blocks, int32_t n_blocks, void* hip_stream,
                         int32_t reps, lof_tuning* out);
 

@@ -966,6 +966,18 @@ lof_status lof_autotune(lof_ctx* c, const lof_block* blocks, int32_t n, void* hi
     t.persistent = 1;
     if (ok) ok = time_run(t, all, &ms1);
     if (ok) best.persistent = ms1 < ms0 ? 1 : 0;
+    // 3) blocks of at most 64 channels and 4096 times: the fused SIR/history
+    //    pass or the row- and column-chunked kernels
+    bool any_post = false;
+    for (int i = 0; i < n && !any_post; ++i) any_post = lofk::post_eligible(blocks[i].n_channels, blocks[i].n_times);
+    if (ok && any_post && !(c->prm.options & LOF_OPT_SIR_PROSE)) {
+      t = best;
+      t.fuse_post = 1;
+      ok = time_run(t, all, &ms0);
+      t.fuse_post = 2;
+      if (ok) ok = time_run(t, all, &ms1);
+      if (ok) best.fuse_post = ms1 < ms0 ? 2 : 1;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

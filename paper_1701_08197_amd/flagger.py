@@ -144,6 +144,12 @@ class Flagger:
         self._check(self._L.lof_autotune(self._h, arr, n, _stream_handle(stream), reps, ctypes.byref(t)))
         return t
 
+    def autotune_raw(self, arr, n: int, stream=None, reps: int = 3) -> N.LofTuning:
+        """lof_autotune on a ctypes lof_block array of n entries."""
+        t = N.LofTuning()
+        self._check(self._L.lof_autotune(self._h, arr, n, _stream_handle(stream), reps, ctypes.byref(t)))
+        return t
+
     def phase_times(self):
         """lof_phase_times: per-phase kernel milliseconds summed over the calls
         since the previous read, and the number of calls (needs
