@@ -566,6 +566,173 @@ __device__ __forceinline__ void integ_flag_series(const IntegSm& s, const uint64
   }
 }
 
+// lane q's 64-bit value (q wave-uniform), each half zero-extended
+__device__ __forceinline__ uint64_t lane_u64(uint64_t x, int q) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, q);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), q);
+  return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+
+// the key of rank r among the first n lanes' keys (ties by lane), wave-uniform
+__device__ __forceinline__ uint64_t wave_rank_key(uint64_t key, int n, int r, int lane) {
+  int rank = 0;
+  for (int q = 0; q < n; ++q) {
+    const uint64_t kq = lane_u64(key, q);
+    rank += (kq < key || (kq == key && q < lane)) ? 1 : 0;
+  }
+  const unsigned long long b = __ballot(lane < n && rank == r);
+  return lane_u64(key, __ffsll(b) - 1);
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+  return x;
+}
+
+// The series of at most 64 values (the spectrum of a block of at most 64
+// channels) flagged by wave 0 alone, value i in lane i: the statistics, the
+// thresholds, SumThreshold and the SIR step of integ_flag_series, with wave
+// shuffles in place of block barriers.  Writes s.mask[0] and s.T; every thread
+// returns the median and stddev.
+template <bool INT>
+__device__ __forceinline__ void integ_flag_series_wave(const IntegSm& s, const uint64_t* vals, int n, int nl,
+                                                       const DevParams& P, double* med_out, double* sd_out) {
+  const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
+  if (wv == 0) {
+    const bool live = lane < n;
+    const uint64_t v = live ? vals[lane] : 0ull;
+    const uint64_t key = integ_key<INT>(v);
+    const int r0 = (n - 1) / 2, r1 = n / 2;
+    const uint64_t k0 = wave_rank_key(key, n, r0, lane);
+    const uint64_t k1 = (r1 == r0) ? k0 : wave_rank_key(key, n, r1, lane);
+    const double v0 = integ_key_value<INT>(k0), v1 = integ_key_value<INT>(k1);
+    const double med = (n & 1) ? v0 : (v0 + v1) / 2.0;
+    double sd;
+    if (P.robust) {
+      // 1.4826 * MAD (integer series: doubled deviations |2v - med2|, exact)
+      uint64_t dk;
+      if (INT) {
+        const uint64_t med2 = k0 + k1;
+        dk = 2 * v > med2 ? 2 * v - med2 : med2 - 2 * v;
+      } else {
+        dk = integ_key<false>((uint64_t)__double_as_longlong(__builtin_fabs(__longlong_as_double((long long)v) - med)));
+      }
+      const uint64_t m0 = wave_rank_key(dk, n, r0, lane);
+      const uint64_t m1 = (r1 == r0) ? m0 : wave_rank_key(dk, n, r1, lane);
+      const double mad = INT ? ((double)m0 + (double)m1) / 4.0
+                             : (integ_key_value<false>(m0) + integ_key_value<false>(m1)) / 2.0;
+      sd = MAD_TO_SIGMA * mad;
+    } else if constexpr (INT) {
+      // exact moments: S1 < 2^53; S2 from the 32-bit halves of the squares' low
+      // words and their high words (sums of 64 stay exact)
+      const unsigned __int128 sq = (unsigned __int128)v * v;
+      const uint64_t lo = (uint64_t)sq, hi = (uint64_t)(sq >> 64);
+      const uint64_t S1 = wave_sum<unsigned long long>(v);
+      const uint64_t A = wave_sum<unsigned long long>(lo & 0xffffffffull);
+      const uint64_t B = wave_sum<unsigned long long>(lo >> 32);
+      const uint64_t Hs = wave_sum<unsigned long long>(hi);
+      const unsigned __int128 S2 = ((unsigned __int128)Hs << 64) + ((unsigned __int128)B << 32) + (unsigned __int128)A;
+      const double mu = (double)S1 / (double)n;
+      const double ex2 = u128_div_rn((uint64_t)(S2 >> 64), (uint64_t)S2, (uint64_t)n);
+      double var = ex2 - mu * mu;
+      if (var < 0.0) var = 0.0;
+      sd = __builtin_sqrt(var);
+    } else {
+      const double x = __longlong_as_double((long long)v);
+      const double S1 = wave_sum<double>(x), S2 = wave_sum<double>(x * x);
+      const double mu = S1 / (double)n, ex2 = S2 / (double)n;
+      double var = ex2 - mu * mu;
+      if (var < 0.0) var = 0.0;
+      sd = __builtin_sqrt(var);
+    }
+    // lane k < max(1, nl) holds the level-k threshold (p^k by k products, as
+    // integ_flag_series forms it)
+    double Tl = 0.0;
+    if (lane < max(1, nl)) {
+      double pk = 1.0;
+      for (int j = 0; j < lane; ++j) pk = pk * P.p;
+      Tl = med + sd * ((P.start * pk / (double)(1 << lane)) * P.sens);
+    }
+    // SumThreshold, level-synchronous, on the prefix sums of the unflagged values
+    uint64_t M = 0;
+    for (int k = 0; k < nl && k < ST_MAX_LEVELS; ++k) {
+      const int I = 1 << k;
+      if (I > n) break;
+      const double Tk = lane_double(Tl, k);
+      const bool keep = live && !((M >> lane) & 1ull);
+      uint64_t Pi = (INT && keep) ? v : 0ull;
+      double Pf = (!INT && keep) ? __longlong_as_double((long long)v) : 0.0;
+      int Pc = keep ? 1 : 0;
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t yi = __shfl_up(Pi, d);
+        const double yf = __shfl_up(Pf, d);
+        const int yc = __shfl_up(Pc, d);
+        if (lane >= d) {
+          Pi += yi;
+          Pf += yf;
+          Pc += yc;
+        }
+      }
+      uint64_t Ei = __shfl_up(Pi, 1);
+      double Ef = __shfl_up(Pf, 1);
+      int Ec = __shfl_up(Pc, 1);
+      if (lane == 0) {
+        Ei = 0ull;
+        Ef = 0.0;
+        Ec = 0;
+      }
+      const int e = min(lane + I - 1, 63);
+      const int c = __shfl(Pc, e) - Ec;
+      bool hit;
+      if (INT) {
+        const int64_t S = (int64_t)(__shfl(Pi, e) - Ei);
+        // floor(c * T_k), FMA-exact, for this window's count
+        const double cd = (double)c, prod = cd * Tk, err = __builtin_fma(cd, Tk, -prod);
+        double fl = __builtin_floor(prod);
+        if (prod == fl && err < 0.0) fl -= 1.0;
+        const int64_t g = fl >= 9.0e18 ? INT64_MAX : (fl <= -9.0e18 ? INT64_MIN : (int64_t)fl);
+        hit = c > 0 && S > g;
+      } else {
+        const double S = __shfl(Pf, e) - Ef;
+        hit = c > 0 && S > (double)c * Tk;
+      }
+      const unsigned long long H = __ballot(hit && lane <= n - I);
+      if (H == 0) continue;
+      uint64_t Wm = H;
+      for (int d = 1; d < I; d <<= 1) Wm |= Wm << d;
+      M |= Wm & lowmask(n);
+    }
+    // SIR step on the series mask
+    if (P.eta_num > 0) {
+      if (P.prose) {
+        const FastDiv fd((uint32_t)P.eta_den);
+        ProseScan f{0u, 0};
+        const uint64_t fw = prose_fwd_word(M, 0, n, f, (uint32_t)P.eta_num, fd);
+        ProseScan r{0u, n};
+        M = fw | prose_bwd_word(M, 0, n, r, (uint32_t)P.eta_num, fd);
+      } else if (P.eta_num >= P.eta_den) {
+        M = lowmask(n);   // eta = 1: every interval qualifies
+      } else if (M != 0) {
+        const int cw = P.eta_den - P.eta_num;
+        const FastDiv fc((uint32_t)cw);
+        M = sir_runs_lane(M, n, P.eta_num, cw, fc);
+      }
+    }
+    if (lane == 0) {
+      s.mask[0] = M;
+      s.red[0] = __double_as_longlong(med);
+      s.red[1] = __double_as_longlong(sd);
+    }
+    if (lane < 16) s.T[lane] = Tl;
+  }
+  __syncthreads();
+  *med_out = __longlong_as_double(s.red[0]);
+  *sd_out = __longlong_as_double(s.red[1]);
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------- the block
 // powers of 8 consecutive samples of a row from t0 (zero past the row's end)
 template <bool INT>
@@ -680,7 +847,8 @@ __device__ __forceinline__ void phase_integrated(const DevBlock& b, const DevPar
   __syncthreads();
   // spectrum: flag along frequency first
   double med, sd;
-  integ_flag_series<INT>(s, s.spec, C, min(P.nl_f, ST_MAX_LEVELS), P, &med, &sd);
+  if (C <= 64) integ_flag_series_wave<INT>(s, s.spec, C, min(P.nl_f, ST_MAX_LEVELS), P, &med, &sd);
+  else integ_flag_series<INT>(s, s.spec, C, min(P.nl_f, ST_MAX_LEVELS), P, &med, &sd);
   for (int i = tid; i < (C + 63) / 64; i += WG) s.cmask[i] = s.mask[i];
   if (INT) {
     // the rows' exact power sums, for the history flagger

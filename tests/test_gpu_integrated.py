@@ -147,3 +147,35 @@ def test_integrated_rejects_long_blocks():
     arr = (N.LofBlock * 1)(P.Block(x, f, P.LOF_CI8, -1).to_c())
     assert fl.flag_blocks_raw(arr, 1) == N.LOF_ERR_INVALID
     fl.close()
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(options=0x10), dict(sir_eta_num=4, sir_eta_den=4),
+                                dict(options=0x10, sir_eta_num=3, sir_eta_den=3), dict(options=0x40),
+                                dict(sir_eta_num=2, sir_eta_den=3, n_levels_freq=4)])
+def test_integrated_spectrum_rfi(kw):
+    """Spectra with many RFI channels (single, adjacent groups, weak and strong)
+    at channel counts on both sides of 64 (one wave or the whole group flags the
+    spectrum): flags and series statistics bit for bit."""
+    say(f"[integrated_spectrum_rfi] {kw}")
+    fl = make(**kw)
+    prm = oracle_params(fl.params)
+    rng = np.random.default_rng(4500 + len(str(kw)))
+    items = []
+    for C in (1, 2, 3, 5, 31, 63, 64, 65, 100, 128):
+        T = int(rng.integers(50, 400))
+        x = synth.ci8_block(rng, C, T).astype(np.int16)
+        for _ in range(int(rng.integers(0, max(1, C // 4) + 1))):
+            c0 = int(rng.integers(0, C))
+            w = int(rng.integers(1, 4))
+            x[c0:c0 + w] *= int(rng.integers(2, 6))
+        items.append((np.clip(x, -127, 127).astype(np.int8), O.CI8, -1))
+    flags, st = run_gpu(fl, items)
+    nfl = 0
+    for (x, _, _), f, s in zip(items, flags, st):
+        r = O.integrated_block(x, O.CI8, prm)
+        assert mismatch(f, r.flags) == 0, x.shape
+        assert s["n_flagged"] == int(r.flags.sum())
+        check_stats(s, r, prm, x.shape[0], x.shape[1])
+        nfl += int(r.flags.any(axis=1).sum())
+    say(f"    flagged channels {nfl}")
+    fl.close()
