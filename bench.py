@@ -594,8 +594,9 @@ def run_config0(args, cores):
     data = torch.from_numpy(x).to(dev)[None]
     flags = torch.empty((1, 64, 4096), dtype=torch.uint8, device=dev)
     arr = block_table(data, flags, 1, NAT.LOF_C64)
+    # enough call slots that the 100 calls of the host-time loop never wait for one
     fl = P.Flagger(P.default_params(max_streams=1, max_channels=64, max_blocks_per_call=1,
-                                    max_samples_per_call=64 * 4096))
+                                    max_samples_per_call=64 * 4096, call_slots=128))
     stream = torch.cuda.current_stream()
     timed_calls(fl, arr, 1, stream, 20)
     ms = timed_calls(fl, arr, 1, stream, max(200, args.steps))

@@ -28,6 +28,7 @@
 #include "lof_integrated.hpp"
 #include "lof_partial.hpp"
 #include "lof_post.hpp"
+#include "lof_stats_split.hpp"
 #include "lof_kernels.hpp"
 
 namespace lofk {
@@ -114,6 +115,8 @@ struct Slot {
   BlockState* d_state = nullptr;
   uint64_t* d_rowsum = nullptr;   // integer rows' power sums [block][max_channels]
   int* d_counter = nullptr;       // persistent-launch work counters, one per launch
+  lofk::SplitState* d_split = nullptr;   // split statistics: nsplit blocks per input kind
+  int nsplit = 0;
   hipEvent_t ev = nullptr;
   bool used = false;
   // LOF_OPT_PHASE_TIMING: event 0 before the first phase kernel, event k after
@@ -148,7 +151,7 @@ constexpr int NVAR = 6;   // time layouts: (integer, float) x (32, 48, 64 lanes)
 // kernels, for occupancy lookups
 enum KernId {
   K_STATS = 0, K_TIME = 2, K_FREQ = 8, K_SIRT = 10, K_SIRF = 13, K_FINAL = 14, K_PROSE = 16, K_INTEG = 18, K_POST = 20,
-  K_STATS_PRE = 22, K_TIME_PRE = 24, K_TIMECX = 30, NKERN = 31
+  K_STATS_PRE = 22, K_TIME_PRE = 24, K_TIMECX = 30, K_SPLIT = 31, NKERN = 35
 };
 int variant_lanes(int v) { return v % 3 == 0 ? 32 : (v % 3 == 1 ? 48 : 64); }
 
@@ -291,6 +294,7 @@ const void* kernel_of(int k) {
   if (k >= K_TIME_PRE && k < K_TIME_PRE + 6)
     return lofk::kernel_time_pre(k < K_TIME_PRE + 3, variant_lanes(k - K_TIME_PRE));
   if (k == K_TIMECX) return lofk::kernel_time_cx();
+  if (k >= K_SPLIT && k < K_SPLIT + 4) return lofk::kernel_stats_split((k - K_SPLIT) % 2 == 0, k - K_SPLIT >= 2);
   return lofk::kernel_final(k == K_FINAL);
 }
 
@@ -302,6 +306,7 @@ void free_slot(Slot& s) {
   if (s.d_state) (void)hipFree(s.d_state);
   if (s.d_rowsum) (void)hipFree(s.d_rowsum);
   if (s.d_counter) (void)hipFree(s.d_counter);
+  if (s.d_split) (void)hipFree(s.d_split);
   if (s.ev) (void)hipEventDestroy(s.ev);
   for (hipEvent_t& e : s.tev)
     if (e) (void)hipEventDestroy(e);
@@ -326,6 +331,12 @@ bool alloc_slot(Slot& s, int max_blocks, int max_channels, size_t mask_words, bo
     for (hipEvent_t& e : s.tev)
       if (hipEventCreate(&e) != hipSuccess) return false;
   if (prose && hipMalloc(&s.d_mask2, sizeof(uint64_t) * mask_words) != hipSuccess) return false;
+  // split statistics: their histograms and pass counters start at zero, and each
+  // call leaves them so
+  s.nsplit = std::min(max_blocks, lofk::SPLIT_MAX_BLOCKS);
+  const size_t split_bytes = sizeof(lofk::SplitState) * 2 * (size_t)s.nsplit;
+  if (hipMalloc(&s.d_split, split_bytes) != hipSuccess || hipMemset(s.d_split, 0, split_bytes) != hipSuccess)
+    return false;
   return hipMalloc(&s.d_desc, sizeof(DevBlock) * max_blocks) == hipSuccess &&
          hipHostMalloc(&s.h_desc, sizeof(DevBlock) * max_blocks, hipHostMallocDefault) == hipSuccess &&
          hipMalloc(&s.d_mask, sizeof(uint64_t) * mask_words) == hipSuccess &&
@@ -522,7 +533,30 @@ void enqueue(lof_ctx* c, const lof_tuning& t, Slot& s, const int* counts, int n,
       continue;
     }
     const bool pre = (c->prm.options & LOF_OPT_PREFLAGGED) != 0;
-    launch(c, t, (pre ? K_STATS_PRE : K_STATS) + kind, LOF_PHASE_STATS, dk, kcnt, 0, s, nc, st, P);
+    // few blocks with a large one among them: each block's statistics split over
+    // workgroups (one launch per radix pass), else one workgroup per block
+    const int64_t big = max_chunks(hk, kcnt, [&](const DevBlock& b) { return (int)std::min<int64_t>(
+                                                   (int64_t)b.C * b.T, INT32_MAX); });
+    if (s.d_split && kcnt <= s.nsplit && big >= lofk::SPLIT_MIN_SAMPLES) {
+      const int mp = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::split_parts(b.C, b.T); });
+      const int np = lofk::split_passes(integer, P.robust != 0);
+      lofk::SplitState* ss = s.d_split + (size_t)kind * s.nsplit;
+      const int kid = K_SPLIT + kind + (pre ? 2 : 0);
+      for (int pass = 0; pass < np; ++pass) {
+        const DevBlock* a_blocks = dk;
+        int a_nb = kcnt, a_mp = mp, a_pass = pass;
+        lofk::SplitState* a_ss = ss;
+        DevParams a_p = P;
+        void* args[] = {&a_blocks, &a_nb, &a_mp, &a_pass, &a_ss, &a_p};
+        (void)hipLaunchKernel(kernel_of(kid), dim3(kcnt * mp), dim3(lofk::WG), args, 0, st);
+      }
+      if (s.tev[0] && s.ntev > 0 && s.ntev < NTEV) {
+        s.tph[s.ntev] = LOF_PHASE_STATS;
+        (void)hipEventRecord(s.tev[s.ntev++], st);
+      }
+    } else {
+      launch(c, t, (pre ? K_STATS_PRE : K_STATS) + kind, LOF_PHASE_STATS, dk, kcnt, 0, s, nc, st, P);
+    }
     int mt[3] = {0, 0, 0};
     for (int j = 0, voff = 0; j < 3; voff += counts[3 * kind + j], ++j) {
       const int cnt = counts[3 * kind + j];

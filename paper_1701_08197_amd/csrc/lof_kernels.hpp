@@ -245,6 +245,80 @@ __device__ uint32_t find_dev_rank(const uint32_t* h, uint32_t med2, uint32_t ran
   return v;
 }
 
+// Median, stddev (or 1.4826 * MAD) and thresholds T_k of a block from its middle
+// order statistics' keys (k0, k1; MAD keys m0, m1) and moments (integer: exact
+// sums S1u, S2u; float: float64 sums S1d, S2d) over its N statistics samples, into
+// sm.median, sm.sigma, sm.T and sm.Tf.  One thread.
+template <bool INT, class SM>
+__device__ __forceinline__ void stats_finish(const DevParams& P, int64_t N, uint32_t k0, uint32_t k1, uint32_t m0,
+                                             uint32_t m1, unsigned long long S1u, unsigned long long S2u, double S1d,
+                                             double S2d, SM& sm) {
+  double v0, v1;
+  if (INT || N == 0) {
+    v0 = (double)k0;
+    v1 = (double)k1;
+  } else {
+    v0 = (double)fkey_inv(k0);
+    v1 = (double)fkey_inv(k1);
+  }
+  const double med = (N & 1) ? v0 : (v0 + v1) / 2.0;
+  const double n = (double)N;
+  double mu, ex2;
+  if (INT) {
+    mu = (double)S1u / n;     // S1, S2 < 2^53: exact conversions
+    ex2 = (double)S2u / n;
+  } else {
+    mu = S1d / n;
+    ex2 = S2d / n;
+  }
+  double var = ex2 - mu * mu;
+  if (var < 0.0 || N == 0) var = 0.0;
+  double sd = __builtin_sqrt(var);
+  if (P.robust && N > 0) {
+    // 1.4826 * MAD; integer input: m0, m1 are doubled deviations
+    double mad;
+    if (INT) mad = ((double)m0 + (double)m1) / 4.0;
+    else mad = (N & 1) ? (double)fkey_inv(m0) : ((double)fkey_inv(m0) + (double)fkey_inv(m1)) / 2.0;
+    sd = MAD_TO_SIGMA * mad;
+  }
+  sm.median = med;
+  sm.sigma = sd;
+  const int nT = max(P.nl_t, P.nl_f);
+  double pk = 1.0;
+  for (int k = 0; k < 16; ++k) {
+    if (k < nT) {
+      const double f = P.start * pk / (double)(1 << k);
+      sm.T[k] = med + sd * (f * P.sens);
+      sm.Tf[k] = (float)sm.T[k];
+      pk = pk * P.p;
+    } else {
+      sm.T[k] = 0.0;
+      sm.Tf[k] = 0.0f;
+    }
+  }
+}
+
+// The statistics of block b (sm.median, sm.sigma, sm.T) into its BlockState and
+// the caller's stats entry (flag totals cleared for the final kernel); threads
+// 0 .. max(18, STATS_BYTES / 8) - 1 of the workgroup
+template <class SM>
+__device__ __forceinline__ void write_block_stats(const DevBlock& b, const DevParams& P, const SM& sm) {
+  const int k = threadIdx.x;
+  if (k < 18) {
+    GLB BlockState* bs = gp<BlockState>(P.bstate) + b.sidx;
+    if (k == 0) bs->median = sm.median;
+    else if (k == 1) bs->sigma = sm.sigma;
+    else bs->T[k - 2] = sm.T[k - 2];
+  }
+  if (P.stats && k < STATS_BYTES / 8) {
+    GLB double* st = (GLB double*)(gp<char>(P.stats) + (int64_t)b.out_idx * STATS_BYTES);
+    if (k == 0) st[0] = sm.median;
+    else if (k == 1) st[1] = sm.sigma;
+    else if (k < 2 + LOF_MAX_LEVELS) st[k] = sm.T[k - 2];
+    else *(GLB long long*)(st + k) = 0;   // flagged samples; history rows and padding
+  }
+}
+
 // PRE: the caller's pre-flagged samples (LOF_OPT_PREFLAGGED) leave every
 // statistic; N is then the number of the others (with none, median and stddev 0)
 template <bool INT, bool PRE, class SM>
@@ -420,49 +494,7 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
       S1d += sm.red_d[0][w];
       S2d += sm.red_d[1][w];
     }
-    double v0, v1;
-    if (INT || N == 0) {
-      v0 = (double)k0;
-      v1 = (double)k1;
-    } else {
-      v0 = (double)fkey_inv(k0);
-      v1 = (double)fkey_inv(k1);
-    }
-    const double med = (N & 1) ? v0 : (v0 + v1) / 2.0;
-    const double n = (double)N;
-    double mu, ex2;
-    if (INT) {
-      mu = (double)S1u / n;     // S1, S2 < 2^53: exact conversions
-      ex2 = (double)S2u / n;
-    } else {
-      mu = S1d / n;
-      ex2 = S2d / n;
-    }
-    double var = ex2 - mu * mu;
-    if (var < 0.0 || N == 0) var = 0.0;
-    double sd = __builtin_sqrt(var);
-    if (P.robust && N > 0) {
-      // 1.4826 * MAD; integer input: m0, m1 are doubled deviations
-      double mad;
-      if (INT) mad = ((double)m0 + (double)m1) / 4.0;
-      else mad = (N & 1) ? (double)fkey_inv(m0) : ((double)fkey_inv(m0) + (double)fkey_inv(m1)) / 2.0;
-      sd = MAD_TO_SIGMA * mad;
-    }
-    sm.median = med;
-    sm.sigma = sd;
-    const int nT = max(P.nl_t, P.nl_f);
-    double pk = 1.0;
-    for (int k = 0; k < 16; ++k) {
-      if (k < nT) {
-        const double f = P.start * pk / (double)(1 << k);
-        sm.T[k] = med + sd * (f * P.sens);
-        sm.Tf[k] = (float)sm.T[k];
-        pk = pk * P.p;
-      } else {
-        sm.T[k] = 0.0;
-        sm.Tf[k] = 0.0f;
-      }
-    }
+    stats_finish<INT>(P, N, k0, k1, m0, m1, S1u, S2u, S1d, S2d, sm);
   }
   __syncthreads();
 }
@@ -2286,20 +2318,7 @@ __global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_stats_kernel(const D
   run_items(nb, counter, [&](int bi) __attribute__((always_inline)) {
     const DevBlock b = blocks[bi];
     phase_stats<INT, PRE>(b, P, sm);
-    const int k = threadIdx.x;
-    if (k < 18) {
-      GLB BlockState* bs = gp<BlockState>(P.bstate) + b.sidx;
-      if (k == 0) bs->median = sm.median;
-      else if (k == 1) bs->sigma = sm.sigma;
-      else bs->T[k - 2] = sm.T[k - 2];
-    }
-    if (P.stats && k < STATS_BYTES / 8) {
-      GLB double* st = (GLB double*)(gp<char>(P.stats) + (int64_t)b.out_idx * STATS_BYTES);
-      if (k == 0) st[0] = sm.median;
-      else if (k == 1) st[1] = sm.sigma;
-      else if (k < 2 + LOF_MAX_LEVELS) st[k] = sm.T[k - 2];
-      else *(GLB long long*)(st + k) = 0;   // flagged samples; history rows and padding
-    }
+    write_block_stats(b, P, sm);
   });
 }
 
