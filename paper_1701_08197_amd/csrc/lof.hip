@@ -151,7 +151,7 @@ constexpr int NVAR = 6;   // time layouts: (integer, float) x (32, 48, 64 lanes)
 // kernels, for occupancy lookups
 enum KernId {
   K_STATS = 0, K_TIME = 2, K_FREQ = 8, K_SIRT = 10, K_SIRF = 13, K_FINAL = 14, K_PROSE = 16, K_INTEG = 18, K_POST = 20,
-  K_STATS_PRE = 22, K_TIME_PRE = 24, K_TIMECX = 30, K_SPLIT = 31, NKERN = 35
+  K_STATS_PRE = 22, K_TIME_PRE = 24, K_TIMECX = 30, K_SPLIT = 31, K_FREQS = 35, NKERN = 36
 };
 int variant_lanes(int v) { return v % 3 == 0 ? 32 : (v % 3 == 1 ? 48 : 64); }
 
@@ -294,6 +294,7 @@ const void* kernel_of(int k) {
   if (k >= K_TIME_PRE && k < K_TIME_PRE + 6)
     return lofk::kernel_time_pre(k < K_TIME_PRE + 3, variant_lanes(k - K_TIME_PRE));
   if (k == K_TIMECX) return lofk::kernel_time_cx();
+  if (k == K_FREQS) return lofk::kernel_freq_small();
   if (k >= K_SPLIT && k < K_SPLIT + 4) return lofk::kernel_stats_split((k - K_SPLIT) % 2 == 0, k - K_SPLIT >= 2);
   return lofk::kernel_final(k == K_FINAL);
 }
@@ -577,7 +578,9 @@ void enqueue(lof_ctx* c, const lof_tuning& t, Slot& s, const int* counts, int n,
       }
     }
     const int mf = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::freq_chunks(integer, b.C, b.T); });
-    launch(c, t, K_FREQ + kind, LOF_PHASE_ST_FREQ, dk, kcnt, mf, s, nc, st, P);
+    // float blocks of at most 16 channels only: the small-slab kernel
+    const bool small = !integer && max_chunks(hk, kcnt, [&](const DevBlock& b) { return b.C; }) <= 16;
+    launch(c, t, small ? K_FREQS : K_FREQ + kind, LOF_PHASE_ST_FREQ, dk, kcnt, mf, s, nc, st, P);
     // blocks of at most 64 channels and 4096 times: SIR, history and flag bytes in
     // one kernel per block with the mask in LDS, when the blocks fill the chip
     // (fewer blocks than CUs: the row- and column-chunked kernels spread them)

@@ -290,11 +290,12 @@ __device__ __forceinline__ int load8(const DevBlock& b, int row, int t0, typenam
   return nv;
 }
 
-// 8 samples with unconditional vector loads: rows 16-byte aligned and t0 + 8 <= T
+// 8 samples from element offset eoff (row * dstride + t0) with unconditional
+// vector loads: rows 16-byte aligned and t0 + 8 <= T
 template <bool INT>
-__device__ __forceinline__ void load8v(const DevBlock& b, int row, int t0, typename PowT<INT>::T (&v)[8]) {
+__device__ __forceinline__ void load8v_off(const DevBlock& b, int64_t eoff, typename PowT<INT>::T (&v)[8]) {
   if (INT) {
-    const GLB uint8_t* rb = gp<const uint8_t>(b.data) + ((int64_t)row * b.dstride + t0) * 2;
+    const GLB uint8_t* rb = gp<const uint8_t>(b.data) + eoff * 2;
     const u32x4 q = *(const GLB u32x4*)rb;
     const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
@@ -303,13 +304,13 @@ __device__ __forceinline__ void load8v(const DevBlock& b, int row, int t0, typen
       v[2 * j + 1] = (typename PowT<INT>::T)ci8_power(w[j] >> 16);
     }
   } else if (b.dtype == 2) {
-    const GLB float* rb = gp<const float>(b.data) + (int64_t)row * b.dstride + t0;
+    const GLB float* rb = gp<const float>(b.data) + eoff;
     const f32x4 a = *(const GLB f32x4*)rb;
     const f32x4 c = *(const GLB f32x4*)(rb + 4);
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
     v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
   } else {
-    const GLB f32x2* rb = gp<const f32x2>(b.data) + (int64_t)row * b.dstride + t0;
+    const GLB f32x2* rb = gp<const f32x2>(b.data) + eoff;
     const bool amp = b.dtype == 3;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -318,6 +319,10 @@ __device__ __forceinline__ void load8v(const DevBlock& b, int row, int t0, typen
       v[2 * j + 1] = amp ? c64_amp(a.z, a.w) : c64_power(a.z, a.w);
     }
   }
+}
+template <bool INT>
+__device__ __forceinline__ void load8v(const DevBlock& b, int row, int t0, typename PowT<INT>::T (&v)[8]) {
+  load8v_off<INT>(b, (int64_t)row * b.dstride + t0, v);
 }
 
 // ---------------------------------------------------------------- shared memory
@@ -385,6 +390,20 @@ struct SmFreq {
     struct {
       TileT t[TE];                 // frequency slab of powers (u16 values / float)
       uint64_t w[TILE_WORDS];      // mask words of the slab
+    } f;
+  } u;
+};
+
+// float slabs of blocks of at most 16 channels: 16 x (NW*64 + 1) powers and the
+// slab's mask words (at most 9 per channel), a third of the generic slab
+struct SmFreqS {
+  int32_t G[ST_MAX_LEVELS][128];
+  double T[16];
+  float Tf[16];
+  union {
+    struct {
+      float t[16 * (NW * 64 + 1)];
+      uint64_t w[16 * 16];
     } f;
   } u;
 };

@@ -6,4 +6,5 @@ namespace lofk {
 const void* kernel_freq(bool integer) {
   return integer ? (const void*)lof_freq_kernel<true> : (const void*)lof_freq_kernel<false>;
 }
+const void* kernel_freq_small() { return (const void*)lof_freq_small_kernel<16>; }
 }  // namespace lofk

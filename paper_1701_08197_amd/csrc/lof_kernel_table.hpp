@@ -11,6 +11,7 @@ const void* kernel_time(bool integer, int lanes);   // lanes: 32, 48 or 64
 const void* kernel_time_pre(bool integer, int lanes);   // starting from pre-flags
 const void* kernel_time_cx();                       // float rows of complex input, 32 lanes
 const void* kernel_freq(bool integer);
+const void* kernel_freq_small();                    // float blocks of at most 16 channels
 const void* kernel_sir_time(int lanes);
 const void* kernel_sir_freq();
 const void* kernel_final(bool integer);

@@ -321,6 +321,11 @@ __device__ __forceinline__ void write_block_stats(const DevBlock& b, const DevPa
 
 // PRE: the caller's pre-flagged samples (LOF_OPT_PREFLAGGED) leave every
 // statistic; N is then the number of the others (with none, median and stddev 0)
+template <bool B>
+struct BoolC {
+  static constexpr bool value = B;
+};
+
 template <bool INT, bool PRE, class SM>
 __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& P, SM& sm) {
   typedef typename PowT<INT>::T VT;
@@ -340,7 +345,7 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
 
   unsigned long long s1u = 0, s2u = 0;
   double s1d = 0.0, s2d = 0.0;
-  constexpr int U = 8;   // chunks of 8 samples in flight per thread
+  constexpr int U = INT ? 8 : 4;   // chunks of 8 samples in flight per thread
   auto consume = [&](const VT (&v)[8], int nv, uint32_t pm) {
     if (PRE) {
       const int live = __popc(~pm & ((1u << nv) - 1u));
@@ -362,9 +367,68 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
       }
     }
   };
-  if (b.aligned && (b.T & 7) == 0) {
-    // every chunk full and aligned: unconditional loads (clamped index, masked
-    // count) so all U loads of a thread are in flight together
+  // rows back to back (row stride = T): chunk it starts at element 8 * it
+  const bool lin = b.dstride == (int64_t)b.T;
+  // integer input, every chunk full and aligned: U raw 16-byte loads in flight per
+  // thread, then per sample the doubled power 2p = sdot4(d, d) with d = (re, im,
+  // re, im): the histogram word of p is at byte offset 2p & ~3 and its counter
+  // is 1 << 16 (p & 1)
+  auto int_chunks = [&](auto lin_c) __attribute__((always_inline)) {
+    constexpr bool LIN = decltype(lin_c)::value;
+    const GLB uint8_t* base8 = gp<const uint8_t>(b.data);
+    auto load = [&](uint32_t it, uint32_t& pm) __attribute__((always_inline)) {
+      int64_t eoff;
+      if constexpr (LIN) {
+        eoff = (int64_t)it * 8;
+        pm = 0u;
+      } else {
+        const int row = (int)fd.div(it);
+        const int t0 = (int)(it - (uint32_t)row * (uint32_t)nch) * 8;
+        eoff = (int64_t)row * b.dstride + t0;
+        pm = pre8<PRE>(b, row, t0, 8);
+      }
+      return *(const GLB u32x4*)(base8 + eoff * 2);
+    };
+    auto add8 = [&](const u32x4& q, uint32_t pm) __attribute__((always_inline)) {
+      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+      uint32_t p2[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const uint32_t d = __builtin_amdgcn_perm(w[m >> 1], w[m >> 1], (m & 1) ? 0x03020302u : 0x01000100u);
+        p2[m] = (uint32_t)__builtin_amdgcn_sdot4((int)d, (int)d, 0, false);
+      }
+      if (PRE) {
+        const int live = __popc(~pm & 0xffu);
+        if (live) atomicAdd(&sm.nlive, (uint32_t)live);
+      }
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        if (PRE && ((pm >> m) & 1u)) continue;
+        atomicAdd((uint32_t*)((unsigned char*)sm.u.ihist + (p2[m] & ~3u)), 1u << ((p2[m] << 3) & 31u));
+      }
+    };
+    uint32_t base = tid;
+    // whole rounds of U chunks: every load issued before the first is used
+    for (; base + (uint32_t)(U - 1) * WG < items; base += (uint32_t)WG * U) {
+      u32x4 q[U];
+      uint32_t pm[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) q[u] = load(base + (uint32_t)u * WG, pm[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) add8(q[u], pm[u]);
+    }
+    for (; base < items; base += WG) {
+      uint32_t pm;
+      const u32x4 q = load(base, pm);
+      add8(q, pm);
+    }
+  };
+  if (INT && b.aligned && (b.T & 7) == 0) {
+    if (lin && !PRE) int_chunks(BoolC<true>{});
+    else int_chunks(BoolC<false>{});
+  } else if (b.aligned && (b.T & 7) == 0) {
+    // float input, every chunk full and aligned: unconditional loads (clamped
+    // index, masked count) so all U loads of a thread are in flight together
     for (uint32_t base = tid; base < items; base += (uint32_t)WG * U) {
       VT v[U][8];
       uint32_t pm[U];
@@ -372,10 +436,15 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
       for (int u = 0; u < U; ++u) {
         const uint32_t it = base + (uint32_t)u * WG;
         const uint32_t ic = it < items ? it : items - 1;
-        const int row = (int)fd.div(ic);
-        const int t0 = (int)(ic - (uint32_t)row * (uint32_t)nch) * 8;
-        load8v<INT>(b, row, t0, v[u]);
-        pm[u] = pre8<PRE>(b, row, t0, 8);
+        if (lin && !PRE) {
+          load8v_off<INT>(b, (int64_t)ic * 8, v[u]);
+          pm[u] = 0u;
+        } else {
+          const int row = (int)fd.div(ic);
+          const int t0 = (int)(ic - (uint32_t)row * (uint32_t)nch) * 8;
+          load8v<INT>(b, row, t0, v[u]);
+          pm[u] = pre8<PRE>(b, row, t0, 8);
+        }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) consume(v[u], base + (uint32_t)u * WG < items ? 8 : 0, pm[u]);
@@ -2312,7 +2381,7 @@ __device__ __forceinline__ void run_items(int nitems, int* counter, F&& f) {
 // Phase A: power, median, stddev and thresholds of each block -> BlockState and
 // the caller's stats entry (whose flag totals the final kernel accumulates).
 template <bool INT, bool PRE>
-__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_stats_kernel(const DevBlock* __restrict__ blocks, int nb,
+__global__ __launch_bounds__(WG, INT ? LOF_WAVES_PER_EU : 8) void lof_stats_kernel(const DevBlock* __restrict__ blocks, int nb,
                                                                          int* counter, DevParams P) {
   __shared__ SmStats<INT> sm;
   run_items(nb, counter, [&](int bi) __attribute__((always_inline)) {
@@ -2362,6 +2431,23 @@ __global__ __launch_bounds__(WG, INT ? LOF_WAVES_PER_EU : float_waves_per_eu) vo
     if (ch >= freq_chunks(INT, b.C, b.T) || b.C <= 1 || P.nl_f <= 1) return;
     load_thresholds<INT>(b, P, sm);
     phase_freq<INT>(b, P, sm, ch);
+  });
+}
+
+// Phase B along frequency, float blocks of at most 16 channels: the generic slab
+// path with a slab of 16 channels, whose smaller LDS and register needs let 4
+// waves per SIMD share a CU
+template <int LF>
+__global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_freq_small_kernel(const DevBlock* __restrict__ blocks,
+                                                                             int nb, int maxch, int* counter,
+                                                                             DevParams P) {
+  __shared__ SmFreqS sm;
+  run_items(nb * maxch, counter, [&](int it) __attribute__((always_inline)) {
+    const int bi = it / maxch, ch = it - bi * maxch;
+    const DevBlock b = blocks[bi];
+    if (ch >= freq_chunks(false, b.C, b.T) || b.C <= 1 || b.C > LF || P.nl_f <= 1) return;
+    load_thresholds<false>(b, P, sm);
+    phase_freq_l<false, LF>(b, P, sm, ch);
   });
 }
 
