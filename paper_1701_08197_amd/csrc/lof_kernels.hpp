@@ -2394,7 +2394,7 @@ __global__ __launch_bounds__(WG, INT ? LOF_WAVES_PER_EU : 8) void lof_stats_kern
 // Phase B, time direction: rows of a block in chunks (CX: float rows of complex
 // input with the formed powers kept, 32 samples per lane)
 template <bool INT, int L, bool CX = false>
-__global__ __launch_bounds__(WG, INT ? LOF_WAVES_PER_EU : float_waves_per_eu) void lof_time_kernel(const DevBlock* __restrict__ blocks, int nb,
+__global__ __launch_bounds__(WG, (INT && L == 64) ? 2 : ((INT || (L == 32 && !CX)) ? LOF_WAVES_PER_EU : float_waves_per_eu)) void lof_time_kernel(const DevBlock* __restrict__ blocks, int nb,
                                                                         int maxch, int* counter, DevParams P) {
   __shared__ SmThr sm;
   run_items(nb * maxch, counter, [&](int it) __attribute__((always_inline)) {
@@ -2408,7 +2408,7 @@ __global__ __launch_bounds__(WG, INT ? LOF_WAVES_PER_EU : float_waves_per_eu) vo
 
 // Phase B, time direction, from caller-supplied pre-flags
 template <bool INT, int L>
-__global__ __launch_bounds__(WG, INT ? LOF_WAVES_PER_EU : float_waves_per_eu) void lof_time_pre_kernel(
+__global__ __launch_bounds__(WG, (INT && L == 64) ? 2 : (INT ? LOF_WAVES_PER_EU : float_waves_per_eu)) void lof_time_pre_kernel(
     const DevBlock* __restrict__ blocks, int nb, int maxch, int* counter, DevParams P) {
   __shared__ SmThr sm;
   run_items(nb * maxch, counter, [&](int it) __attribute__((always_inline)) {
@@ -2453,7 +2453,7 @@ __global__ __launch_bounds__(WG, LOF_WAVES_PER_EU) void lof_freq_small_kernel(co
 
 // Phase C: SIR operator along time (rows in chunks), then along frequency (slabs)
 template <int L>
-__global__ __launch_bounds__(WG, LOF_SIRT_WAVES_PER_EU) void lof_sir_time_kernel(const DevBlock* __restrict__ blocks, int nb,
+__global__ __launch_bounds__(WG, L == 64 ? 2 : LOF_SIRT_WAVES_PER_EU) void lof_sir_time_kernel(const DevBlock* __restrict__ blocks, int nb,
                                                                             int maxch, int* counter, DevParams P) {
   __shared__ SmSirT sm;
   run_items(nb * maxch, counter, [&](int it) __attribute__((always_inline)) {

@@ -183,3 +183,21 @@ def test_split_state_clears_between_calls_and_graph_replays():
             exact_stats(s, r, 7)
             assert mismatch(f.cpu().numpy(), r.flags) == 0, (rep, x.shape)
     fg.close()
+
+
+def test_split_at_the_block_limit():
+    """64 blocks of a kind (the most a split launch takes) with one large block
+    among small ones of many shapes, in a context whose call limit is 64: every
+    block exact against the oracle."""
+    say("[split_at_the_block_limit]")
+    fl = make(max_blocks_per_call=64)
+    prm = oracle_params(fl.params)
+    rng = np.random.default_rng(8500)
+    shapes = [(64, 3072)] + [(int(rng.integers(1, 40)), int(rng.integers(1, 700))) for _ in range(63)]
+    items = [(synth.ci8_block(rng, C, T), O.CI8, -1) for C, T in shapes]
+    flags, st = run_gpu(fl, items)
+    for (x, _, _), f, s in zip(items, flags, st):
+        r = O.flag_block(x, O.CI8, prm)
+        exact_stats(s, r, 7)
+        assert mismatch(f, r.flags) == 0, x.shape
+    fl.close()
