@@ -239,10 +239,11 @@ lof_status lof_create(const lof_params* params, int hip_device, lof_ctx** out);
  * flagger reads only the committed history of that id and stages one value per
  * channel for lof_history_update (a fully flagged channel stages nothing); a
  * second flag call for the same id before the commit replaces the staged values.
- * n_blocks = 0 is a no-op.  A call of at most 64 blocks of an input kind whose
- * largest block has 65536 samples or more computes those blocks' statistics
- * over many workgroups (a few more launches, same results: bit-exact for
- * complex int8, the float64 moment sums in another order for float input).
+ * n_blocks = 0 is a no-op.  A call with at most 4 float blocks whose largest
+ * has 65536 samples or more, or at most 16 whose largest has 2^20, computes
+ * their statistics over many workgroups (a few more launches; the float64
+ * moment sums are added in another order, so the stddev may differ in its last
+ * bits from a call that takes one workgroup per block).
  * Errors: LOF_ERR_INVALID (null ctx/blocks, bad shape,
  * stride, dtype, stream id out of range or repeated), LOF_ERR_CAPACITY (more
  * blocks or samples than the create-time maxima, C > max_channels). */

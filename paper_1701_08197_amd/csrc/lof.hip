@@ -115,7 +115,7 @@ struct Slot {
   BlockState* d_state = nullptr;
   uint64_t* d_rowsum = nullptr;   // integer rows' power sums [block][max_channels]
   int* d_counter = nullptr;       // persistent-launch work counters, one per launch
-  lofk::SplitState* d_split = nullptr;   // split statistics: nsplit blocks per input kind
+  lofk::SplitState* d_split = nullptr;   // split statistics of up to nsplit float blocks
   int nsplit = 0;
   hipEvent_t ev = nullptr;
   bool used = false;
@@ -151,7 +151,7 @@ constexpr int NVAR = 6;   // time layouts: (integer, float) x (32, 48, 64 lanes)
 // kernels, for occupancy lookups
 enum KernId {
   K_STATS = 0, K_TIME = 2, K_FREQ = 8, K_SIRT = 10, K_SIRF = 13, K_FINAL = 14, K_PROSE = 16, K_INTEG = 18, K_POST = 20,
-  K_STATS_PRE = 22, K_TIME_PRE = 24, K_TIMECX = 30, K_SPLIT = 31, K_FREQS = 35, NKERN = 36
+  K_STATS_PRE = 22, K_TIME_PRE = 24, K_TIMECX = 30, K_SPLIT = 31, K_FREQS = 33, NKERN = 34
 };
 int variant_lanes(int v) { return v % 3 == 0 ? 32 : (v % 3 == 1 ? 48 : 64); }
 
@@ -295,7 +295,7 @@ const void* kernel_of(int k) {
     return lofk::kernel_time_pre(k < K_TIME_PRE + 3, variant_lanes(k - K_TIME_PRE));
   if (k == K_TIMECX) return lofk::kernel_time_cx();
   if (k == K_FREQS) return lofk::kernel_freq_small();
-  if (k >= K_SPLIT && k < K_SPLIT + 4) return lofk::kernel_stats_split((k - K_SPLIT) % 2 == 0, k - K_SPLIT >= 2);
+  if (k == K_SPLIT || k == K_SPLIT + 1) return lofk::kernel_stats_split(k == K_SPLIT + 1);
   return lofk::kernel_final(k == K_FINAL);
 }
 
@@ -335,7 +335,7 @@ bool alloc_slot(Slot& s, int max_blocks, int max_channels, size_t mask_words, bo
   // split statistics: their histograms and pass counters start at zero, and each
   // call leaves them so
   s.nsplit = std::min(max_blocks, lofk::SPLIT_MAX_BLOCKS);
-  const size_t split_bytes = sizeof(lofk::SplitState) * 2 * (size_t)s.nsplit;
+  const size_t split_bytes = sizeof(lofk::SplitState) * (size_t)s.nsplit;
   if (hipMalloc(&s.d_split, split_bytes) != hipSuccess || hipMemset(s.d_split, 0, split_bytes) != hipSuccess)
     return false;
   return hipMalloc(&s.d_desc, sizeof(DevBlock) * max_blocks) == hipSuccess &&
@@ -534,15 +534,15 @@ void enqueue(lof_ctx* c, const lof_tuning& t, Slot& s, const int* counts, int n,
       continue;
     }
     const bool pre = (c->prm.options & LOF_OPT_PREFLAGGED) != 0;
-    // few blocks with a large one among them: each block's statistics split over
-    // workgroups (one launch per radix pass), else one workgroup per block
+    // a few float blocks with a large one among them: each block's statistics
+    // split over workgroups (one launch per radix pass), else one workgroup per block
     const int64_t big = max_chunks(hk, kcnt, [&](const DevBlock& b) { return (int)std::min<int64_t>(
                                                    (int64_t)b.C * b.T, INT32_MAX); });
-    if (s.d_split && kcnt <= s.nsplit && big >= lofk::SPLIT_MIN_SAMPLES) {
+    if (!integer && s.d_split && kcnt <= s.nsplit && lofk::split_chosen(kcnt, big)) {
       const int mp = max_chunks(hk, kcnt, [&](const DevBlock& b) { return lofk::split_parts(b.C, b.T); });
-      const int np = lofk::split_passes(integer, P.robust != 0);
-      lofk::SplitState* ss = s.d_split + (size_t)kind * s.nsplit;
-      const int kid = K_SPLIT + kind + (pre ? 2 : 0);
+      const int np = lofk::split_passes(P.robust != 0);
+      lofk::SplitState* ss = s.d_split;
+      const int kid = K_SPLIT + (pre ? 1 : 0);
       for (int pass = 0; pass < np; ++pass) {
         const DevBlock* a_blocks = dk;
         int a_nb = kcnt, a_mp = mp, a_pass = pass;

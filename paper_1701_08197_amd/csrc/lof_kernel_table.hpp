@@ -6,7 +6,7 @@
 namespace lofk {
 const void* kernel_stats(bool integer);
 const void* kernel_stats_pre(bool integer);         // statistics without pre-flagged samples
-const void* kernel_stats_split(bool integer, bool pre);   // statistics of large blocks, one part per workgroup
+const void* kernel_stats_split(bool pre);           // statistics of large float blocks, one part per workgroup
 const void* kernel_time(bool integer, int lanes);   // lanes: 32, 48 or 64
 const void* kernel_time_pre(bool integer, int lanes);   // starting from pre-flags
 const void* kernel_time_cx();                       // float rows of complex input, 32 lanes

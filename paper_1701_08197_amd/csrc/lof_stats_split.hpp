@@ -1,26 +1,29 @@
-// lof_stats_split.hpp -- statistics of a large block split over workgroups
+// lof_stats_split.hpp -- statistics of large float blocks split over workgroups
 // (gfx950).
 //
 // Method: van Nieuwpoort, "Towards exascale real-time RFI mitigation", arXiv
 // 1701.08197, Sec. 2.1 (thresholds from the block's median and stddev), Sec. 4.2
 // (an O(N) median; the MAD as the robust stddev).
 //
-// A call with few blocks leaves most of the chip idle while one workgroup per
-// block computes its statistics.  Here a block's samples are cut into parts of
-// about SPLIT_PART_ITEMS chunks of 8 samples, one workgroup per part, and the
-// median (and the MAD) is a radix select whose passes are separate launches:
+// The one-workgroup statistics of a float block are a 3-pass radix select over
+// its samples on one CU (a 262144-sample block: about 0.25 ms), so a call with
+// few large float blocks waits on a few CUs.  Here a block's samples are cut
+// into parts of about SPLIT_PART_ITEMS chunks of 8 samples, one workgroup per
+// part, and each radix pass is a launch of its own:
 //   - every part histograms its samples' current key digit in LDS (the keys whose
 //     higher digits match the prefixes chosen so far) and adds its nonzero bins
-//     to the block's global histogram; pass 0 also writes the part's moments and
-//     count of statistics samples;
+//     to the block's global histogram; pass 0 also writes the part's float64
+//     moments and count of statistics samples;
 //   - the part that finishes last (a device-scope counter) picks the digit of
 //     ranks r0 and r1 from the global histogram, clears it for the next pass, and
-//     after the last pass forms median, stddev and thresholds exactly as the
-//     one-workgroup kernel does (integer input: the same exact sums; float input:
-//     float64 part sums added in part order, so the stddev may differ from the
-//     one-workgroup kernel's in its last bits).
-// Digits: integer power (16 bits) 8 + 8; integer doubled deviation (<= 2^17, a
-// 20-bit key) 12 + 8; float keys (32 bits) 12 + 12 + 8.
+//     after the last pass forms median, stddev and thresholds with the code of
+//     the one-workgroup kernel (the part sums are added in part order, so the
+//     stddev may differ from the one-workgroup kernel's in its last bits).
+// Keys: the order-preserving 32-bit key of the float32 power (the MAD: of the
+// absolute deviation from the median), digits 12 + 12 + 8.  Integer input keeps
+// the one-workgroup kernel: its exact full-resolution histogram is faster than
+// this split at every call size measured (the split's global histogram merges
+// contend on the few bins where noise powers crowd).
 #pragma once
 #include "lof_kernels.hpp"
 
@@ -28,14 +31,26 @@ namespace lofk {
 
 constexpr int SPLIT_MAX_PARTS = 64;
 constexpr int SPLIT_PART_ITEMS = 1024;      // chunks of 8 samples per part (at least, below 64 parts)
-constexpr int SPLIT_MAX_BLOCKS = 64;        // blocks of one kind in a split launch
-constexpr int64_t SPLIT_MIN_SAMPLES = 65536;   // the host splits calls whose largest block reaches this
+constexpr int SPLIT_MAX_BLOCKS = 16;        // float blocks of a call that take the split path
+constexpr int64_t SPLIT_MIN_SAMPLES = 65536;   // the largest of them (up to 4 blocks)
+constexpr int64_t SPLIT_BIG_SAMPLES = 1 << 20; // the largest of them (5 to 16 blocks)
+constexpr int SPLIT_PASSES = 3;             // radix passes of one order statistic
 
-// per block of a split launch, in call scratch; hist, done are zero between passes
+// The host's choice: a call's float blocks take the split statistics when there
+// are at most 4 of them and the largest has at least 65536 samples, or at most 16
+// and the largest has at least 2^20 (measured: 1 or 4 blocks of 64 x 4096
+// complex64 take 0.20 / 0.24 ms instead of 0.34 / 0.35 ms per call, 1 or 8 blocks
+// of 256 x 12000 float32 0.33 / 0.72 ms instead of 2.1 / 2.3 ms; 16 blocks of
+// 64 x 4096 are faster on one workgroup each).
+__host__ __device__ inline bool split_chosen(int nblocks, int64_t largest) {
+  return (nblocks <= 4 && largest >= SPLIT_MIN_SAMPLES) || (nblocks <= SPLIT_MAX_BLOCKS && largest >= SPLIT_BIG_SAMPLES);
+}
+
+// per block of a split launch, in call scratch; hist and done are zero between
+// passes
 struct SplitState {
   uint32_t hist[2][HBINS];
-  unsigned long long pu[SPLIT_MAX_PARTS][2];   // integer part sums of p and p^2
-  double pd[SPLIT_MAX_PARTS][2];               // float part sums of p and p^2
+  double pd[SPLIT_MAX_PARTS][2];               // part sums of p and p^2
   uint32_t plive[SPLIT_MAX_PARTS];             // statistics samples per part
   uint32_t done;                               // parts finished in this pass
   uint32_t N;                                  // statistics samples of the block
@@ -49,30 +64,12 @@ __host__ __device__ inline int split_parts(int C, int T) {
   const int64_t p = (items + SPLIT_PART_ITEMS - 1) / SPLIT_PART_ITEMS;
   return (int)(p < 1 ? 1 : (p > SPLIT_MAX_PARTS ? SPLIT_MAX_PARTS : p));
 }
-// radix passes of the median (and, robust, of the MAD)
-__host__ __device__ inline int split_select_passes(bool integer) { return integer ? 2 : 3; }
-__host__ __device__ inline int split_passes(bool integer, bool robust) {
-  return split_select_passes(integer) * (robust ? 2 : 1);
-}
-// digit of pass j of a select: bits [lo, lo + db) of a key of kb bits
-__host__ __device__ inline void split_digit(bool integer, bool dev, int j, int& kb, int& lo, int& db) {
-  if (integer) {
-    kb = dev ? 20 : 16;
-    const int w0 = dev ? 12 : 8;
-    db = j == 0 ? w0 : 8;
-    lo = j == 0 ? kb - w0 : 0;
-  } else {
-    kb = 32;
-    db = j < 2 ? 12 : 8;
-    lo = kb - 12 * (j + 1);
-    if (j == 2) lo = 0;
-  }
-}
+// launches of the median (and, robust, of the MAD)
+__host__ __device__ inline int split_passes(bool robust) { return SPLIT_PASSES * (robust ? 2 : 1); }
 
 struct SmSplit {
   uint32_t hist[2][HBINS];
   double red_d[2][NW];
-  unsigned long long red_u[2][NW];
   uint32_t red_n[NW];
   uint32_t scan[NW];
   uint32_t sel[4];
@@ -82,40 +79,29 @@ struct SmSplit {
   double median, sigma;
 };
 
-template <bool INT, bool PRE>
+template <bool PRE>
 __device__ __forceinline__ void phase_stats_split(const DevBlock& b, const DevParams& P, SplitState& ss, int part,
                                                   int pass, SmSplit& sm) {
-  typedef typename PowT<INT>::T VT;
   const int tid = thread_id(), lane = tid & 63, wv = tid >> 6;
   const int parts = split_parts(b.C, b.T);
-  const int nsel = split_select_passes(INT);
-  const bool dev = pass >= nsel;
-  const int j = dev ? pass - nsel : pass;
-  int kb, lo, db;
-  split_digit(INT, dev, j, kb, lo, db);
-  const uint32_t dmask = (1u << db) - 1u;
+  const bool dev = pass >= SPLIT_PASSES;            // the MAD's passes
+  const int j = dev ? pass - SPLIT_PASSES : pass;   // digit of this pass: 12, 12, 8 bits
+  const int db = j < 2 ? 12 : 8;
+  const int lo = j < 2 ? 20 - 12 * j : 0;
   const int hi = lo + db;
+  const uint32_t dmask = (1u << db) - 1u;
   // the previous passes' results (written by earlier launches)
   const uint32_t pre0 = j ? ss.pre0 : 0u, pre1 = j ? ss.pre1 : 0u;
   const bool two = j > 0 && pre1 != pre0;
   const bool skip = pass > 0 && ss.N == 0;   // nothing to select
-  uint32_t med2 = 0;
   double med = 0.0;
   if (dev) {
     const uint32_t k0 = ss.k0, k1 = ss.k1, N = ss.N;
-    med2 = k0 + k1;
-    if (!INT) {
-      const double v0 = (double)fkey_inv(k0), v1 = (double)fkey_inv(k1);
-      med = (N & 1) ? v0 : (v0 + v1) / 2.0;
-    }
+    const double v0 = (double)fkey_inv(k0), v1 = (double)fkey_inv(k1);
+    med = (N & 1) ? v0 : (v0 + v1) / 2.0;
   }
-  auto key = [&](VT v) -> uint32_t {
-    if (!dev) return INT ? (uint32_t)v : fkey((float)v);
-    if (INT) {
-      const int d = 2 * (int)(uint32_t)v - (int)med2;
-      return (uint32_t)(d < 0 ? -d : d);
-    }
-    return fkey((float)__builtin_fabs((double)v - med));
+  auto key = [&](float v) -> uint32_t {
+    return dev ? fkey((float)__builtin_fabs((double)v - med)) : fkey(v);
   };
 
   for (int i = tid; i < 2 * HBINS; i += WG) (&sm.hist[0][0])[i] = 0u;
@@ -125,33 +111,26 @@ __device__ __forceinline__ void phase_stats_split(const DevBlock& b, const DevPa
   const FastDiv fd((uint32_t)nch);
   const uint32_t per = (items + (uint32_t)parts - 1u) / (uint32_t)parts;
   const uint32_t it0 = (uint32_t)part * per, it1 = min(items, it0 + per);
-  unsigned long long s1u = 0, s2u = 0;
   double s1d = 0.0, s2d = 0.0;
   uint32_t live = 0;
   if (!skip) {
     for (uint32_t it = it0 + (uint32_t)tid; it < it1; it += WG) {
       const int row = (int)fd.div(it);
       const int t0 = (int)(it - (uint32_t)row * (uint32_t)nch) * 8;
-      VT v[8];
-      const int nv = load8<INT>(b, row, t0, v);
+      float v[8];
+      const int nv = load8<false>(b, row, t0, v);
       const uint32_t pm = pre8<PRE>(b, row, t0, nv);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         if (q < nv && !((pm >> q) & 1u)) {
           if (pass == 0) {
             ++live;
-            if (INT) {
-              const uint32_t p = (uint32_t)v[q];
-              s1u += p;
-              s2u += (unsigned long long)(p * p);   // p <= 32768: p*p <= 2^30
-            } else {
-              const double d = (double)v[q];
-              s1d += d;
-              s2d += d * d;
-            }
+            const double d = (double)v[q];
+            s1d += d;
+            s2d += d * d;
           }
           const uint32_t kv = key(v[q]);
-          const uint32_t top = hi >= kb ? 0u : (kv >> hi);
+          const uint32_t top = hi >= 32 ? 0u : (kv >> hi);
           const uint32_t dg = (kv >> lo) & dmask;
           if (top == pre0) atomicAdd(&sm.hist[0][dg], 1u);
           if (two && top == pre1) atomicAdd(&sm.hist[1][dg], 1u);
@@ -168,33 +147,24 @@ __device__ __forceinline__ void phase_stats_split(const DevBlock& b, const DevPa
   if (pass == 0) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
-      s1u += __shfl_xor(s1u, d);
-      s2u += __shfl_xor(s2u, d);
       s1d += __shfl_xor(s1d, d);
       s2d += __shfl_xor(s2d, d);
       live += __shfl_xor(live, d);
     }
     if (lane == 0) {
-      sm.red_u[0][wv] = s1u;
-      sm.red_u[1][wv] = s2u;
       sm.red_d[0][wv] = s1d;
       sm.red_d[1][wv] = s2d;
       sm.red_n[wv] = live;
     }
     __syncthreads();
     if (tid == 0) {
-      unsigned long long a = 0, c = 0;
       double x = 0.0, y = 0.0;
       uint32_t n = 0;
       for (int w = 0; w < NW; ++w) {
-        a += sm.red_u[0][w];
-        c += sm.red_u[1][w];
         x += sm.red_d[0][w];
         y += sm.red_d[1][w];
         n += sm.red_n[w];
       }
-      ss.pu[part][0] = a;
-      ss.pu[part][1] = c;
       ss.pd[part][0] = x;
       ss.pd[part][1] = y;
       ss.plive[part] = n;
@@ -231,7 +201,6 @@ __device__ __forceinline__ void phase_stats_split(const DevBlock& b, const DevPa
     find_bin(two ? sm.hist[1] : sm.hist[0], r1, sm, b1, q1);
   }
   const uint32_t np0 = (pre0 << db) | b0, np1 = (pre1 << db) | b1;
-  const bool sel_done = j == nsel - 1;
   if (tid == 0) {
     ss.done = 0u;
     ss.N = N;
@@ -239,36 +208,28 @@ __device__ __forceinline__ void phase_stats_split(const DevBlock& b, const DevPa
     ss.pre1 = np1;
     ss.r0 = q0;
     ss.r1 = q1;
-    if (sel_done && !dev) {
+    if (j == SPLIT_PASSES - 1 && !dev) {
       ss.k0 = np0;
       ss.k1 = np1;
     }
   }
-  if (pass != split_passes(INT, P.robust != 0) - 1) return;
+  if (pass != split_passes(P.robust != 0) - 1) return;
   // the last pass: the block's statistics
   if (tid == 0) {
-    unsigned long long S1u = 0, S2u = 0;
     double S1d = 0.0, S2d = 0.0;
     for (int q = 0; q < parts; ++q) {
-      S1u += ss.pu[q][0];
-      S2u += ss.pu[q][1];
       S1d += ss.pd[q][0];
       S2d += ss.pd[q][1];
     }
-    uint32_t k0, k1, m0 = 0, m1 = 0;
+    uint32_t k0 = np0, k1 = np1, m0 = 0, m1 = 0;
     if (dev) {
       k0 = ss.k0;
       k1 = ss.k1;
       m0 = np0;
       m1 = np1;
-    } else {
-      k0 = np0;
-      k1 = np1;
     }
-    if (N == 0) {
-      k0 = k1 = m0 = m1 = 0u;
-    }
-    stats_finish<INT>(P, (int64_t)N, k0, k1, m0, m1, S1u, S2u, S1d, S2d, sm);
+    if (N == 0) k0 = k1 = m0 = m1 = 0u;
+    stats_finish<false>(P, (int64_t)N, k0, k1, m0, m1, 0ull, 0ull, S1d, S2d, sm);
   }
   __syncthreads();
   write_block_stats(b, P, sm);
