@@ -115,6 +115,7 @@ struct Slot {
   BlockState* d_state = nullptr;
   uint64_t* d_rowsum = nullptr;   // integer rows' power sums [block][max_channels]
   int* d_counter = nullptr;       // persistent-launch work counters, one per launch
+  uint32_t* d_cand = nullptr;     // float statistics: candidate keys, CAND_PER_WORD per mask word
   lofk::SplitState* d_split = nullptr;   // split statistics of up to nsplit float blocks
   int nsplit = 0;
   hipEvent_t ev = nullptr;
@@ -240,6 +241,7 @@ DevParams dev_params(const lof_ctx* c, uint64_t* mask, uint64_t* mask2, BlockSta
   P.bstate = state;
   P.rowsum = rowsum;
   P.stats = stats;
+  P.cand = nullptr;
   return P;
 }
 
@@ -308,6 +310,7 @@ void free_slot(Slot& s) {
   if (s.d_rowsum) (void)hipFree(s.d_rowsum);
   if (s.d_counter) (void)hipFree(s.d_counter);
   if (s.d_split) (void)hipFree(s.d_split);
+  if (s.d_cand) (void)hipFree(s.d_cand);
   if (s.ev) (void)hipEventDestroy(s.ev);
   for (hipEvent_t& e : s.tev)
     if (e) (void)hipEventDestroy(e);
@@ -338,6 +341,7 @@ bool alloc_slot(Slot& s, int max_blocks, int max_channels, size_t mask_words, bo
   const size_t split_bytes = sizeof(lofk::SplitState) * (size_t)s.nsplit;
   if (hipMalloc(&s.d_split, split_bytes) != hipSuccess || hipMemset(s.d_split, 0, split_bytes) != hipSuccess)
     return false;
+  if (hipMalloc(&s.d_cand, sizeof(uint32_t) * lofk::CAND_PER_WORD * mask_words) != hipSuccess) return false;
   return hipMalloc(&s.d_desc, sizeof(DevBlock) * max_blocks) == hipSuccess &&
          hipHostMalloc(&s.h_desc, sizeof(DevBlock) * max_blocks, hipHostMallocDefault) == hipSuccess &&
          hipMalloc(&s.d_mask, sizeof(uint64_t) * mask_words) == hipSuccess &&
@@ -511,7 +515,8 @@ int max_chunks(const DevBlock* h, int n, F&& f) {
 // still in s.h_desc, which sizes the chunked launches)
 void enqueue(lof_ctx* c, const lof_tuning& t, Slot& s, const int* counts, int n, void* stats, hipStream_t st,
              bool autocommit, bool timing = false) {
-  const DevParams P = dev_params(c, s.d_mask, s.d_mask2, s.d_state, s.d_rowsum, stats);
+  DevParams P = dev_params(c, s.d_mask, s.d_mask2, s.d_state, s.d_rowsum, stats);
+  P.cand = s.d_cand;
   if (t.persistent) hipLaunchKernelGGL(lofk::lof_zero_kernel, dim3(1), dim3(64), 0, st, s.d_counter, NCOUNTER);
   s.ntev = 0;
   if (timing && s.tev[0] && hipEventRecord(s.tev[0], st) == hipSuccess) s.ntev = 1;

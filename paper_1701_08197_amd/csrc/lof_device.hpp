@@ -144,7 +144,13 @@ struct DevParams {
   BlockState* bstate;    // per-block statistics of this call
   uint64_t* rowsum;      // integer input: [block sidx][maxC] power sum of each row
   void* stats;           // lof_block_stats* or null
+  uint32_t* cand;        // float statistics: CAND_PER_WORD keys per mask word (null: none)
 };
+
+// float statistics: candidate keys of the last radix pass kept per mask word of
+// the block (a block's list holds up to CAND_PER_WORD * C * ceil(T / 64) keys,
+// about N / 8)
+constexpr int CAND_PER_WORD = 8;
 
 // ---------------------------------------------------------------- cross-lane
 // DPP moves with bound_ctrl: a lane whose source is outside the wave reads 0.
@@ -365,6 +371,7 @@ struct SmStats {
   uint32_t scan[NW];
   uint32_t sel[4];
   uint32_t nlive;                            // samples not pre-flagged
+  uint32_t ncand;                            // candidate keys of the last radix pass
   double median, sigma;
 };
 

@@ -134,16 +134,22 @@ __device__ __forceinline__ float fkey_inv(uint32_t k) {
 // Radix select of the order statistics r0 <= r1 over the block's keys
 // key(power) of KB bits (16: 12 + 4, 32: 12 + 12 + 8).  If have_pass0, hist[0]
 // already holds the first-digit histogram.
+// cand (32-bit keys, 3 passes only): the middle pass also writes the keys it
+// histograms (those whose first digit is a chosen one) to the block's candidate
+// list, up to ccap of them; if all fit, the last pass reads the list instead of
+// the block.
 template <bool INT, int KB, bool PRE, class SM, class KF>
 __device__ __forceinline__ void radix_select_k(const DevBlock& b, SM& sm, uint32_t r0, uint32_t r1, bool have_pass0,
-                                               KF key, uint32_t& k0, uint32_t& k1) {
+                                               KF key, uint32_t& k0, uint32_t& k1, GLB uint32_t* cand = nullptr,
+                                               uint32_t ccap = 0) {
   typedef typename PowT<INT>::T VT;
-  const int tid = thread_id();
+  const int tid = thread_id(), lane = tid & 63;
   const int nch = (b.T + 7) >> 3;
   const uint32_t items = (uint32_t)b.C * (uint32_t)nch;
   const FastDiv fd((uint32_t)nch);
   const int npass = KB == 16 ? 2 : 3;
   const int dbits[3] = {12, KB == 16 ? 4 : 12, 8};
+  const bool use_cand = KB == 32 && cand != nullptr && ccap > 0;
   uint32_t pre0 = 0, pre1 = 0;
   int hi = KB;
   for (int pass = 0; pass < npass; ++pass) {
@@ -152,22 +158,46 @@ __device__ __forceinline__ void radix_select_k(const DevBlock& b, SM& sm, uint32
     const uint32_t dmask = (1u << db) - 1u;
     if (pass > 0 || !have_pass0) {
       for (int i = tid; i < 2 * HBINS; i += WG) (&sm.u.hist[0][0])[i] = 0u;
+      if (tid == 0 && pass == 1) sm.ncand = 0u;
       __syncthreads();
       const bool two = pre1 != pre0;
-      for (uint32_t it = tid; it < items; it += WG) {
-        const int row = (int)fd.div(it);
-        const int t0 = (int)(it - (uint32_t)row * (uint32_t)nch) * 8;
-        VT v[8];
-        const int nv = load8<INT>(b, row, t0, v);
-        const uint32_t pm = pre8<PRE>(b, row, t0, nv);
+      const bool collect = use_cand && pass == 1;
+      auto add = [&](uint32_t kv) __attribute__((always_inline)) {
+        const uint32_t top = pass == 0 ? 0u : (kv >> hi);
+        const uint32_t dg = (kv >> lo) & dmask;
+        if (top == pre0) atomicAdd(&sm.u.hist[0][dg], 1u);
+        if (two && top == pre1) atomicAdd(&sm.u.hist[1][dg], 1u);
+      };
+      if (use_cand && pass == 2 && sm.ncand <= ccap) {
+        // the candidates of the middle pass instead of the block
+        const uint32_t nc = sm.ncand;
+        for (uint32_t i = tid; i < nc; i += WG) add(cand[i]);
+      } else {
+        for (uint32_t it = tid; it < items; it += WG) {
+          const int row = (int)fd.div(it);
+          const int t0 = (int)(it - (uint32_t)row * (uint32_t)nch) * 8;
+          VT v[8];
+          const int nv = load8<INT>(b, row, t0, v);
+          const uint32_t pm = pre8<PRE>(b, row, t0, nv);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          if (j < nv && !((pm >> j) & 1u)) {
-            const uint32_t kv = key(v[j]);
-            const uint32_t top = pass == 0 ? 0u : (kv >> hi);
-            const uint32_t dg = (kv >> lo) & dmask;
-            if (top == pre0) atomicAdd(&sm.u.hist[0][dg], 1u);
-            if (two && top == pre1) atomicAdd(&sm.u.hist[1][dg], 1u);
+          for (int j = 0; j < 8; ++j) {
+            const bool live = j < nv && !((pm >> j) & 1u);
+            const uint32_t kv = live ? key(v[j]) : 0u;
+            if (live) add(kv);
+            if (collect) {
+              // one LDS atomic per wave for the wave's candidates
+              const uint32_t top = kv >> hi;
+              const bool c = live && (top == pre0 || top == pre1);
+              const unsigned long long bal = __ballot(c);
+              if (bal) {
+                const int lead = __ffsll(bal) - 1;
+                uint32_t base = 0;
+                if (lane == lead) base = atomicAdd(&sm.ncand, (uint32_t)__popcll(bal));
+                base = (uint32_t)__shfl(base, lead);
+                const uint32_t idx = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+                if (c && idx < ccap) cand[idx] = kv;
+              }
+            }
           }
         }
       }
@@ -189,10 +219,11 @@ __device__ __forceinline__ void radix_select_k(const DevBlock& b, SM& sm, uint32
 
 template <bool INT, bool PRE, class SM>
 __device__ __forceinline__ void radix_select(const DevBlock& b, SM& sm, uint32_t r0, uint32_t r1, bool have_pass0,
-                                             uint32_t& k0, uint32_t& k1) {
+                                             uint32_t& k0, uint32_t& k1, GLB uint32_t* cand = nullptr,
+                                             uint32_t ccap = 0) {
   typedef typename PowT<INT>::T VT;
   radix_select_k<INT, INT ? 16 : 32, PRE>(b, sm, r0, r1, have_pass0,
-                                     [](VT v) { return INT ? (uint32_t)v : fkey((float)v); }, k0, k1);
+                                     [](VT v) { return INT ? (uint32_t)v : fkey((float)v); }, k0, k1, cand, ccap);
 }
 
 // Robust stddev (Sec. 4.2 lists the MAD): the value of rank `rank` among the
@@ -522,6 +553,10 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
   }
   __syncthreads();
 
+  // the block's candidate list for the last pass of a 3-pass radix select (in the
+  // call's candidate scratch at the block's mask-word offset; null: read the block)
+  GLB uint32_t* cand = P.cand ? gp<uint32_t>(P.cand) + b.mask_off * CAND_PER_WORD : nullptr;
+  const uint32_t ccap = (uint32_t)b.C * (uint32_t)((b.T + 63) >> 6) * (uint32_t)CAND_PER_WORD;
   uint32_t k0 = 0, k1 = 0;
   if (N == 0) {
     // every sample pre-flagged: no statistics (median and stddev 0)
@@ -529,7 +564,7 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
     k0 = find_bin16(sm.u.ihist, r0, sm);
     k1 = (r1 == r0) ? k0 : find_bin16(sm.u.ihist, r1, sm);
   } else {
-    radix_select<INT, PRE>(b, sm, r0, r1, !INT, k0, k1);
+    radix_select<INT, PRE>(b, sm, r0, r1, !INT, k0, k1, cand, ccap);
   }
   // robust stddev: the middle order statistics of the deviations from the median
   uint32_t m0 = 0, m1 = 0;
@@ -543,14 +578,14 @@ __device__ __forceinline__ void phase_stats(const DevBlock& b, const DevParams& 
         radix_select_k<INT, 32, PRE>(b, sm, r0, r1, false, [med2](VT v) {
           const int d = 2 * (int)(uint32_t)v - (int)med2;
           return (uint32_t)(d < 0 ? -d : d);
-        }, m0, m1);
+        }, m0, m1, cand, ccap);
       }
     } else {
       const double v0 = (double)fkey_inv(k0), v1 = (double)fkey_inv(k1);
       const double med = (N & 1) ? v0 : (v0 + v1) / 2.0;
       radix_select_k<INT, 32, PRE>(b, sm, r0, r1, false, [med](VT v) {
         return fkey((float)__builtin_fabs((double)v - med));
-      }, m0, m1);
+      }, m0, m1, cand, ccap);
     }
   }
 
