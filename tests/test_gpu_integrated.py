@@ -179,3 +179,29 @@ def test_integrated_spectrum_rfi(kw):
         nfl += int(r.flags.any(axis=1).sum())
     say(f"    flagged channels {nfl}")
     fl.close()
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(options=0x40), dict(options=0x10, sir_eta_num=2, sir_eta_den=5)])
+def test_integrated_every_channel_count(kw):
+    """Every channel count from 1 to 66 (the spectrum flagged by one wave up to
+    64 channels, odd and even counts for the two middle ranks, then by the whole
+    group): flags and series statistics bit for bit."""
+    say(f"[integrated_every_channel_count] {kw}")
+    fl = make(max_blocks_per_call=70, **kw)
+    prm = oracle_params(fl.params)
+    rng = np.random.default_rng(4700 + len(str(kw)))
+    items = []
+    for C in range(1, 67):
+        T = int(rng.integers(20, 120))
+        x = synth.ci8_block(rng, C, T).astype(np.int16)
+        for _ in range(int(rng.integers(0, C // 5 + 1))):
+            c0 = int(rng.integers(0, C))
+            x[c0:c0 + int(rng.integers(1, 3))] *= int(rng.integers(2, 5))
+        items.append((np.clip(x, -127, 127).astype(np.int8), O.CI8, -1))
+    flags, st = run_gpu(fl, items)
+    for (x, _, _), f, s in zip(items, flags, st):
+        r = O.integrated_block(x, O.CI8, prm)
+        assert mismatch(f, r.flags) == 0, x.shape
+        assert s["n_flagged"] == int(r.flags.sum())
+        check_stats(s, r, prm, x.shape[0], x.shape[1])
+    fl.close()
